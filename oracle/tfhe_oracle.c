@@ -1,0 +1,680 @@
+/*
+ * CPU oracle for TFHE gate bootstrapping — TEST INFRASTRUCTURE ONLY.
+ * See tfhe_oracle.h for what each part follows.  Everything here is the plain
+ * definition: schoolbook negacyclic products in wrapping uint32 arithmetic, no
+ * transform, no blocking, no fusion.  Threads only run independent gates side
+ * by side; they never change what a gate computes.
+ */
+#define _GNU_SOURCE
+#include "tfhe_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based generator.                                                  */
+/* The mixing function is the SplitMix64 output function (Steele, Lea, Flood, */
+/* "Fast splittable pseudorandom number generators", OOPSLA 2014), with its   */
+/* published constants.  draw(seed, stream, idx) feeds it a Weyl sequence:   */
+/*   base = mix(seed + GAMMA*(stream+1)),  draw = mix(base + GAMMA*(idx+1)).  */
+/* ------------------------------------------------------------------------ */
+#define OR_GAMMA 0x9E3779B97F4A7C15ULL
+
+uint64_t or_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t idx) {
+    uint64_t base = or_mix64(seed + OR_GAMMA * (stream + 1));
+    return or_mix64(base + OR_GAMMA * (idx + 1));
+}
+
+/* Box-Muller, cosine branch, one standard normal from draws 2*idx, 2*idx+1. */
+double or_gaussian(uint64_t seed, uint64_t stream, uint64_t idx) {
+    uint64_t x = or_draw(seed, stream, 2 * idx);
+    uint64_t y = or_draw(seed, stream, 2 * idx + 1);
+    double u1 = (double)((x >> 11) + 1) * 0x1.0p-53; /* (0, 1] */
+    double u2 = (double)(y >> 11) * 0x1.0p-53;       /* [0, 1) */
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+/* A real number in (-1/2, 1/2) as a Torus32 word: round(x * 2^32), ties to even. */
+uint32_t or_torus_from_double(double x) {
+    return (uint32_t)(int64_t)nearbyint(x * 4294967296.0);
+}
+
+/* Streams of the generator (one per kind of random quantity). */
+enum { ST_LWE_KEY = 1, ST_TLWE_KEY = 2, ST_BK_MASK = 3, ST_BK_NOISE = 4,
+       ST_KSK_MASK = 5, ST_KSK_NOISE = 6, ST_ENC_MASK = 7, ST_ENC_NOISE = 8 };
+
+static uint32_t top_word(uint64_t d) { return (uint32_t)(d >> 32); }
+static int32_t top_bit(uint64_t d) { return (int32_t)(d >> 63); }
+
+/* ------------------------------------------------------------------------ */
+/* Parameters: TFHE's 110-bit gate-bootstrapping set (paper Sec. VII, "same   */
+/* as the existing implementation of TFHE").                                  */
+/* ------------------------------------------------------------------------ */
+void or_default_params(or_params* P) {
+    P->n = 500;
+    P->N = 1024;
+    P->bk_l = 2;
+    P->bk_bgbit = 10;
+    P->ks_t = 8;
+    P->ks_basebit = 2;
+    P->lwe_stdev = 2.44e-5;
+    P->bk_stdev = 7.18e-9;
+}
+
+/* mu = 1/8 on the torus: a bit b is encrypted as +mu (b = 1) or -mu (b = 0). */
+#define OR_MU 0x20000000u
+
+static int log2i(int32_t v) {
+    int r = 0;
+    while ((1 << r) < v) r++;
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ring Z/2^32[X]/(X^N + 1).                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Schoolbook negacyclic product:
+ *   (P*Q)_m = sum_{j+k=m} P_j Q_k  -  sum_{j+k=m+N} P_j Q_k   (mod 2^32),
+ * because X^N = -1.  Wrapping uint32 multiply-add is exact mod 2^32. */
+void or_negacyclic_mul(int32_t N, const uint32_t* P, const uint32_t* Q, uint32_t* out) {
+    uint32_t* acc = (uint32_t*)calloc((size_t)N, sizeof(uint32_t));
+    for (int32_t j = 0; j < N; j++) {
+        uint32_t pj = P[j];
+        for (int32_t k = 0; k < N - j; k++) acc[j + k] += pj * Q[k];
+        for (int32_t k = N - j; k < N; k++) acc[j + k - N] -= pj * Q[k];
+    }
+    memcpy(out, acc, (size_t)N * sizeof(uint32_t));
+    free(acc);
+}
+
+/* out = X^a * P for a in [0, 2N): the coefficient at j moves to j + a, with a
+ * sign flip each time it passes X^N. */
+void or_rotate(int32_t N, const uint32_t* P, int32_t a, uint32_t* out) {
+    int32_t twoN = 2 * N;
+    a %= twoN;
+    if (a < 0) a += twoN;
+    for (int32_t j = 0; j < N; j++) {
+        int32_t e = j + a;
+        if (e >= twoN) e -= twoN;
+        if (e < N) out[e] = P[j];
+        else out[e - N] = (uint32_t)0 - P[j];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gadget decomposition (TFHE, signed balanced digits of Bgbit bits):        */
+/*   x~ = x + sum_p (Bg/2) 2^(32-Bgbit(p+1)) + 2^(32-l*Bgbit-1)                */
+/*   d_p = ((x~ >> (32 - Bgbit(p+1))) & (Bg-1)) - Bg/2,   p = 0..l-1          */
+/* so that x ~= sum_p d_p 2^(32-Bgbit(p+1)) with |error| <= 2^(32-l*Bgbit-1). */
+/* ------------------------------------------------------------------------ */
+void or_gadget_decompose(const or_params* P, uint32_t x, int32_t* digits) {
+    uint32_t Bg = 1u << P->bk_bgbit;
+    uint32_t half = Bg / 2;
+    uint32_t offset = 1u << (32 - P->bk_l * P->bk_bgbit - 1);
+    for (int p = 0; p < P->bk_l; p++) offset += half << (32 - P->bk_bgbit * (p + 1));
+    uint32_t xt = x + offset;
+    for (int p = 0; p < P->bk_l; p++) {
+        uint32_t field = (xt >> (32 - P->bk_bgbit * (p + 1))) & (Bg - 1);
+        digits[p] = (int32_t)field - (int32_t)half;
+    }
+}
+
+/* Modulus switch to Z_2N: round(x * 2N / 2^32) mod 2N, ties rounded up. */
+uint32_t or_modswitch(const or_params* P, uint32_t x) {
+    int s = 32 - log2i(2 * P->N);
+    return (x + (1u << (s - 1))) >> s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gate linear combination: out = (0, kappa) + s1*c1 + s2*c2 over all n+1     */
+/* words.  The constants put the true inputs' phase in (0, 1/2).             */
+/* ------------------------------------------------------------------------ */
+void or_gate_combine(const or_params* P, int op, const uint32_t* c1,
+                     const uint32_t* c2, uint32_t* out) {
+    const uint32_t mu = OR_MU;
+    uint32_t kappa;
+    int32_t s1, s2;
+    switch (op) {
+    case OR_AND:   kappa = 0u - mu;      s1 = 1;  s2 = 1;  break;
+    case OR_NAND:  kappa = mu;           s1 = -1; s2 = -1; break;
+    case OR_OR:    kappa = mu;           s1 = 1;  s2 = 1;  break;
+    case OR_NOR:   kappa = 0u - mu;      s1 = -1; s2 = -1; break;
+    case OR_XOR:   kappa = 2u * mu;      s1 = 2;  s2 = 2;  break;
+    case OR_XNOR:  kappa = 0u - 2u * mu; s1 = -2; s2 = -2; break;
+    case OR_ANDNY: kappa = 0u - mu;      s1 = -1; s2 = 1;  break;
+    case OR_ANDYN: kappa = 0u - mu;      s1 = 1;  s2 = -1; break;
+    case OR_ORNY:  kappa = mu;           s1 = -1; s2 = 1;  break;
+    case OR_ORYN:  kappa = mu;           s1 = 1;  s2 = -1; break;
+    default:       kappa = 0;            s1 = 0;  s2 = 0;  break;
+    }
+    for (int32_t i = 0; i <= P->n; i++)
+        out[i] = (uint32_t)s1 * c1[i] + (uint32_t)s2 * c2[i];
+    out[P->n] += kappa;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keys.                                                                      */
+/* ------------------------------------------------------------------------ */
+static size_t bk_words(const or_params* P) {
+    return (size_t)P->n * (size_t)(2 * P->bk_l) * 2u * (size_t)P->N;
+}
+static size_t ksk_words(const or_params* P) {
+    return (size_t)P->N * (size_t)P->ks_t * (size_t)(1u << P->ks_basebit) * (size_t)(P->n + 1);
+}
+
+int or_keygen(const or_params* P, uint64_t seed, const int32_t* lwe_key_in,
+              const int32_t* tlwe_key_in, or_keys* K) {
+    const int32_t n = P->n, N = P->N, L2 = 2 * P->bk_l, t = P->ks_t;
+    const uint32_t B = 1u << P->ks_basebit;
+    memset(K, 0, sizeof(*K));
+    K->P = *P;
+    K->seed = seed;
+    K->lwe_key = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    K->tlwe_key = (int32_t*)malloc((size_t)N * sizeof(int32_t));
+    K->bk = (uint32_t*)calloc(bk_words(P), sizeof(uint32_t));
+    K->ksk = (uint32_t*)calloc(ksk_words(P), sizeof(uint32_t));
+    if (!K->lwe_key || !K->tlwe_key || !K->bk || !K->ksk) { or_keys_free(K); return -2; }
+
+    /* Binary keys: the top bit of each draw. */
+    for (int32_t i = 0; i < n; i++)
+        K->lwe_key[i] = lwe_key_in ? lwe_key_in[i] : top_bit(or_draw(seed, ST_LWE_KEY, (uint64_t)i));
+    for (int32_t j = 0; j < N; j++)
+        K->tlwe_key[j] = tlwe_key_in ? tlwe_key_in[j] : top_bit(or_draw(seed, ST_TLWE_KEY, (uint64_t)j));
+
+    /* Bootstrapping key: BK_i = TGSW(s_i).  Row r = 2j + p is a TLWE sample of
+     * zero (A_r uniform, B_r = A_r*S + E_r) plus s_i * 2^(32-Bgbit(p+1)) added to
+     * coefficient 0 of column j. */
+    uint32_t* S = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t* AS = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    for (int32_t j = 0; j < N; j++) S[j] = (uint32_t)K->tlwe_key[j];
+    for (int32_t i = 0; i < n; i++) {
+        for (int32_t r = 0; r < L2; r++) {
+            uint32_t* rowA = K->bk + (((size_t)i * L2 + r) * 2 + 0) * N;
+            uint32_t* rowB = K->bk + (((size_t)i * L2 + r) * 2 + 1) * N;
+            uint64_t base = ((uint64_t)i * L2 + (uint64_t)r) * (uint64_t)N;
+            for (int32_t c = 0; c < N; c++) rowA[c] = top_word(or_draw(seed, ST_BK_MASK, base + c));
+            or_negacyclic_mul(N, rowA, S, AS);
+            for (int32_t c = 0; c < N; c++)
+                rowB[c] = AS[c] + or_torus_from_double(P->bk_stdev * or_gaussian(seed, ST_BK_NOISE, base + c));
+            int32_t j = r / P->bk_l, p = r % P->bk_l;
+            uint32_t h = 1u << (32 - P->bk_bgbit * (p + 1));
+            uint32_t* col = (j == 0) ? rowA : rowB;
+            col[0] += (uint32_t)K->lwe_key[i] * h;
+        }
+    }
+    free(S);
+    free(AS);
+
+    /* Key-switching key: KSK[i][jj][v] = LWE_s(v * s'_i * 2^(32-basebit(jj+1)))
+     * for v = 1..B-1, with s' the extracted key (the TLWE key coefficients);
+     * KSK[i][jj][0] is the all-zero sample. */
+    for (int32_t i = 0; i < N; i++) {
+        for (int32_t jj = 0; jj < t; jj++) {
+            for (uint32_t v = 1; v < B; v++) {
+                uint32_t* row = K->ksk + (((size_t)i * t + jj) * B + v) * (size_t)(n + 1);
+                uint64_t sample = ((uint64_t)i * t + (uint64_t)jj) * (B - 1) + (v - 1);
+                uint32_t body = 0;
+                for (int32_t l = 0; l < n; l++) {
+                    row[l] = top_word(or_draw(seed, ST_KSK_MASK, sample * (uint64_t)n + l));
+                    body += row[l] * (uint32_t)K->lwe_key[l];
+                }
+                uint32_t msg = v * (uint32_t)K->tlwe_key[i] * (1u << (32 - P->ks_basebit * (jj + 1)));
+                body += or_torus_from_double(P->lwe_stdev * or_gaussian(seed, ST_KSK_NOISE, sample));
+                row[n] = body + msg;
+            }
+        }
+    }
+    return 0;
+}
+
+void or_keys_free(or_keys* K) {
+    free(K->lwe_key);
+    free(K->tlwe_key);
+    free(K->bk);
+    free(K->ksk);
+    K->lwe_key = NULL;
+    K->tlwe_key = NULL;
+    K->bk = NULL;
+    K->ksk = NULL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* LWE encryption / phase / decryption (paper Sec. II-A: B = A.S + e).       */
+/* Ciphertext q = nonce + c of a call draws its mask from stream 7 at        */
+/* q*n + l and its noise from stream 8 at q.                                 */
+/* ------------------------------------------------------------------------ */
+void or_encrypt_bits(const or_keys* K, const uint8_t* bits, size_t count,
+                     uint64_t nonce, uint32_t* ct) {
+    const int32_t n = K->P.n;
+    for (size_t c = 0; c < count; c++) {
+        uint64_t q = nonce + (uint64_t)c;
+        uint32_t* s = ct + c * (size_t)(n + 1);
+        uint32_t body = 0;
+        for (int32_t l = 0; l < n; l++) {
+            s[l] = top_word(or_draw(K->seed, ST_ENC_MASK, q * (uint64_t)n + l));
+            body += s[l] * (uint32_t)K->lwe_key[l];
+        }
+        body += or_torus_from_double(K->P.lwe_stdev * or_gaussian(K->seed, ST_ENC_NOISE, q));
+        body += bits[c] ? OR_MU : (0u - OR_MU);
+        s[n] = body;
+    }
+}
+
+void or_phase(const or_keys* K, const uint32_t* ct, size_t count, int32_t* phase) {
+    const int32_t n = K->P.n;
+    for (size_t c = 0; c < count; c++) {
+        const uint32_t* s = ct + c * (size_t)(n + 1);
+        uint32_t dot = 0;
+        for (int32_t l = 0; l < n; l++) dot += s[l] * (uint32_t)K->lwe_key[l];
+        phase[c] = (int32_t)(s[n] - dot);
+    }
+}
+
+void or_decrypt_bits(const or_keys* K, const uint32_t* ct, size_t count, uint8_t* bits) {
+    int32_t* ph = (int32_t*)malloc(count * sizeof(int32_t) + 1);
+    or_phase(K, ct, count, ph);
+    for (size_t c = 0; c < count; c++) bits[c] = ph[c] > 0 ? 1 : 0;
+    free(ph);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bootstrapping.                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* One CMux step of the blind rotation on accumulator acc = [a(X) | b(X)]:
+ *   D = X^abar * acc - acc,
+ *   acc[c] += sum_{j, p} digit_p(D_j) * BK_i[2j+p][c]   for c = 0, 1.
+ * bk_i points at BK_i laid out [2l][2][N]. */
+void or_external_product_cmux(const or_params* P, const uint32_t* bk_i,
+                              int32_t abar, uint32_t* acc) {
+    const int32_t N = P->N, l = P->bk_l;
+    uint32_t* rot = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t* D = (uint32_t*)malloc(2u * (size_t)N * sizeof(uint32_t));
+    uint32_t* dig = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t* prod = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t* sum = (uint32_t*)calloc(2u * (size_t)N, sizeof(uint32_t));
+    int32_t digits[32];
+    for (int32_t j = 0; j < 2; j++) {
+        or_rotate(N, acc + (size_t)j * N, abar, rot);
+        for (int32_t m = 0; m < N; m++) D[(size_t)j * N + m] = rot[m] - acc[(size_t)j * N + m];
+    }
+    for (int32_t j = 0; j < 2; j++) {
+        for (int32_t p = 0; p < l; p++) {
+            for (int32_t m = 0; m < N; m++) {
+                or_gadget_decompose(P, D[(size_t)j * N + m], digits);
+                dig[m] = (uint32_t)digits[p];
+            }
+            int32_t r = 2 * j + p;
+            for (int32_t c = 0; c < 2; c++) {
+                or_negacyclic_mul(N, dig, bk_i + ((size_t)r * 2 + c) * N, prod);
+                for (int32_t m = 0; m < N; m++) sum[(size_t)c * N + m] += prod[m];
+            }
+        }
+    }
+    for (int32_t m = 0; m < 2 * N; m++) acc[m] += sum[m];
+    free(rot);
+    free(D);
+    free(dig);
+    free(prod);
+    free(sum);
+}
+
+/* Blind rotation of the test vector v = sum_j mu X^j:
+ *   acc = (0, X^(2N - bbar) v);  for i < n: CMux with BK_i and abar_i.
+ * lwe_in is the gate's combined sample (n+1 words). */
+void or_blind_rotate(const or_keys* K, const uint32_t* lwe_in, uint32_t* acc) {
+    const or_params* P = &K->P;
+    const int32_t n = P->n, N = P->N, L2 = 2 * P->bk_l;
+    uint32_t* v = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    for (int32_t j = 0; j < N; j++) v[j] = OR_MU;
+    int32_t bbar = (int32_t)or_modswitch(P, lwe_in[n]);
+    memset(acc, 0, (size_t)N * sizeof(uint32_t));
+    or_rotate(N, v, 2 * N - bbar, acc + N);
+    for (int32_t i = 0; i < n; i++) {
+        int32_t abar = (int32_t)or_modswitch(P, lwe_in[i]);
+        or_external_product_cmux(P, K->bk + (size_t)i * L2 * 2 * N, abar, acc);
+    }
+    free(v);
+}
+
+/* Sample extraction of coefficient 0: a'_0 = a_0, a'_m = -a_(N-m), b' = b_0. */
+void or_sample_extract(const or_params* P, const uint32_t* acc, uint32_t* lwe_big) {
+    const int32_t N = P->N;
+    lwe_big[0] = acc[0];
+    for (int32_t m = 1; m < N; m++) lwe_big[m] = (uint32_t)0 - acc[N - m];
+    lwe_big[N] = acc[N];
+}
+
+/* Key switching N -> n with unsigned base-2^basebit digits of a'_i rounded to
+ * t*basebit bits:  out = (0, b') - sum_{i, jj} KSK[i][jj][d_{i,jj}]. */
+void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out) {
+    const or_params* P = &K->P;
+    const int32_t n = P->n, N = P->N, t = P->ks_t, bb = P->ks_basebit;
+    const uint32_t B = 1u << bb;
+    const uint32_t round_off = 1u << (32 - t * bb - 1);
+    for (int32_t l = 0; l < n; l++) out[l] = 0;
+    out[n] = lwe_big[N];
+    for (int32_t i = 0; i < N; i++) {
+        uint32_t xt = lwe_big[i] + round_off;
+        for (int32_t jj = 0; jj < t; jj++) {
+            uint32_t d = (xt >> (32 - bb * (jj + 1))) & (B - 1);
+            const uint32_t* row = K->ksk + (((size_t)i * t + jj) * B + d) * (size_t)(n + 1);
+            for (int32_t l = 0; l <= n; l++) out[l] -= row[l];
+        }
+    }
+}
+
+void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,
+                       const uint32_t* c2, uint32_t* out) {
+    const or_params* P = &K->P;
+    uint32_t* comb = (uint32_t*)malloc((size_t)(P->n + 1) * sizeof(uint32_t));
+    uint32_t* acc = (uint32_t*)malloc(2u * (size_t)P->N * sizeof(uint32_t));
+    uint32_t* big = (uint32_t*)malloc((size_t)(P->N + 1) * sizeof(uint32_t));
+    or_gate_combine(P, op, c1, c2, comb);
+    or_blind_rotate(K, comb, acc);
+    or_sample_extract(P, acc, big);
+    or_key_switch(K, big, out);
+    free(comb);
+    free(acc);
+    free(big);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Running independent gates on several threads.                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_keys* K;
+    const uint8_t* ops;
+    const uint32_t* const* in0;
+    const uint32_t* const* in1;
+    uint32_t* const* out;
+    size_t count;
+    size_t next;
+    pthread_mutex_t lock;
+} gate_job;
+
+static void* gate_worker(void* arg) {
+    gate_job* J = (gate_job*)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        size_t g = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (g >= J->count) break;
+        or_bootstrap_gate(J->K, J->ops[g], J->in0[g], J->in1[g], J->out[g]);
+    }
+    return NULL;
+}
+
+static int resolve_threads(int threads) {
+    if (threads > 0) return threads;
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    return c > 0 ? (int)c : 1;
+}
+
+/* Runs gate g on (in0[g], in1[g]) -> out[g] for g < count, pointer form. */
+static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* const* in0,
+                      const uint32_t* const* in1, uint32_t* const* out, size_t count,
+                      int threads) {
+    if (count == 0) return;
+    gate_job J;
+    J.K = K;
+    J.ops = ops;
+    J.in0 = in0;
+    J.in1 = in1;
+    J.out = out;
+    J.count = count;
+    J.next = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    int T = resolve_threads(threads);
+    if ((size_t)T > count) T = (int)count;
+    pthread_t* tid = (pthread_t*)malloc((size_t)T * sizeof(pthread_t));
+    for (int i = 0; i < T; i++) pthread_create(&tid[i], NULL, gate_worker, &J);
+    for (int i = 0; i < T; i++) pthread_join(tid[i], NULL);
+    free(tid);
+    pthread_mutex_destroy(&J.lock);
+}
+
+void or_bootstrap_gates(const or_keys* K, const uint8_t* ops, const uint32_t* in0,
+                        const uint32_t* in1, uint32_t* out, size_t count, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    const uint32_t** a = (const uint32_t**)malloc((count + 1) * sizeof(*a));
+    const uint32_t** b = (const uint32_t**)malloc((count + 1) * sizeof(*b));
+    uint32_t** o = (uint32_t**)malloc((count + 1) * sizeof(*o));
+    for (size_t g = 0; g < count; g++) {
+        a[g] = in0 + g * W;
+        b[g] = in1 + g * W;
+        o[g] = out + g * W;
+    }
+    run_gates(K, ops, a, b, o, count, threads);
+    free(a);
+    free(b);
+    free(o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Circuits as gate lists over wires (each wire holds one LWE sample).        */
+/* ------------------------------------------------------------------------ */
+typedef struct { int op, in0, in1, out; } or_gate_t;
+typedef struct { or_gate_t* g; long ng, cap; long nwires; } or_prog;
+
+static long new_wire(or_prog* pr) { return pr->nwires++; }
+
+static long emit(or_prog* pr, int op, long a, long b) {
+    if (pr->ng == pr->cap) {
+        pr->cap = pr->cap ? 2 * pr->cap : 256;
+        pr->g = (or_gate_t*)realloc(pr->g, (size_t)pr->cap * sizeof(or_gate_t));
+    }
+    long o = new_wire(pr);
+    or_gate_t* G = &pr->g[pr->ng++];
+    G->op = op;
+    G->in0 = (int)a;
+    G->in1 = (int)b;
+    G->out = (int)o;
+    return o;
+}
+
+/* Ripple-carry adder of eqs. (1)-(2), sum modulo 2^w (carry out dropped):
+ *   bit 0:     r = a ^ b,            c = a & b
+ *   bit i:     t = a ^ b, g = a & b, r = t ^ c, h = t & c, c = g | h
+ *   bit w-1:   t = a ^ b,            r = t ^ c                              */
+static void build_add(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    if (w <= 0) return;
+    if (w == 1) { r[0] = emit(pr, OR_XOR, a[0], b[0]); return; }
+    r[0] = emit(pr, OR_XOR, a[0], b[0]);
+    long c = emit(pr, OR_AND, a[0], b[0]);
+    for (int i = 1; i < w; i++) {
+        long t = emit(pr, OR_XOR, a[i], b[i]);
+        if (i == w - 1) { r[i] = emit(pr, OR_XOR, t, c); break; }
+        long g = emit(pr, OR_AND, a[i], b[i]);
+        r[i] = emit(pr, OR_XOR, t, c);
+        long h = emit(pr, OR_AND, t, c);
+        c = emit(pr, OR_OR, g, h);
+    }
+}
+
+/* Naive multiplication (Sec. III-B-1) keeping the low w bits:
+ *   acc = A & b_0;  for i >= 1: acc[i..w-1] += (A & b_i)[0..w-1-i]. */
+static void build_mul(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    long* acc = (long*)malloc((size_t)w * sizeof(long));
+    long* pp = (long*)malloc((size_t)w * sizeof(long));
+    long* sum = (long*)malloc((size_t)w * sizeof(long));
+    for (int j = 0; j < w; j++) acc[j] = emit(pr, OR_AND, a[j], b[0]);
+    for (int i = 1; i < w; i++) {
+        int m = w - i;
+        for (int j = 0; j < m; j++) pp[j] = emit(pr, OR_AND, a[j], b[i]);
+        build_add(pr, acc + i, pp, m, sum);
+        for (int j = 0; j < m; j++) acc[i + j] = sum[j];
+    }
+    memcpy(r, acc, (size_t)w * sizeof(long));
+    free(acc);
+    free(pp);
+    free(sum);
+}
+
+/* Tree accumulation (Sec. V-B-2, Fig. 4): the list is split into its first
+ * and second halves, which are added element-wise; an odd last element is
+ * carried to the next round unchanged. */
+static void build_tree_sum(or_prog* pr, long* vals, int count, int w, long* r) {
+    int len = count;
+    long* tmp = (long*)malloc((size_t)w * sizeof(long));
+    while (len > 1) {
+        int h = len / 2;
+        for (int k = 0; k < h; k++) {
+            build_add(pr, vals + (size_t)k * w, vals + (size_t)(k + h) * w, w, tmp);
+            memcpy(vals + (size_t)k * w, tmp, (size_t)w * sizeof(long));
+        }
+        if (len & 1) memcpy(vals + (size_t)h * w, vals + (size_t)(len - 1) * w, (size_t)w * sizeof(long));
+        len = h + (len & 1);
+    }
+    memcpy(r, vals, (size_t)w * sizeof(long));
+    free(tmp);
+}
+
+/* Evaluates a program: wires 0..ninputs-1 hold the inputs; each gate runs
+ * once all its inputs exist, gates whose inputs are ready run side by side. */
+static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    long* level = (long*)calloc((size_t)pr->nwires, sizeof(long));
+    long maxlev = 0;
+    for (long k = 0; k < pr->ng; k++) {
+        const or_gate_t* G = &pr->g[k];
+        long l0 = level[G->in0], l1 = level[G->in1];
+        level[G->out] = 1 + (l0 > l1 ? l0 : l1);
+        if (level[G->out] > maxlev) maxlev = level[G->out];
+    }
+    uint8_t* ops = (uint8_t*)malloc((size_t)pr->ng + 1);
+    const uint32_t** a = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*a));
+    const uint32_t** b = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*b));
+    uint32_t** o = (uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*o));
+    for (long L = 1; L <= maxlev; L++) {
+        size_t cnt = 0;
+        for (long k = 0; k < pr->ng; k++) {
+            const or_gate_t* G = &pr->g[k];
+            if (level[G->out] != L) continue;
+            ops[cnt] = (uint8_t)G->op;
+            a[cnt] = wires + (size_t)G->in0 * W;
+            b[cnt] = wires + (size_t)G->in1 * W;
+            o[cnt] = wires + (size_t)G->out * W;
+            cnt++;
+        }
+        run_gates(K, ops, a, b, o, cnt, threads);
+    }
+    free(level);
+    free(ops);
+    free(a);
+    free(b);
+    free(o);
+}
+
+enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2 };
+
+static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
+                           uint32_t* R, size_t count, int32_t width, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    or_prog pr = {0};
+    pr.nwires = (long)(2 * count * (size_t)width);
+    long* outw = (long*)malloc(count * (size_t)width * sizeof(long));
+    long* ia = (long*)malloc((size_t)width * sizeof(long));
+    long* ib = (long*)malloc((size_t)width * sizeof(long));
+    for (size_t c = 0; c < count; c++) {
+        for (int32_t k = 0; k < width; k++) {
+            ia[k] = (long)(c * width + k);
+            ib[k] = (long)((count + c) * width + k);
+        }
+        if (kind == KIND_ADD) build_add(&pr, ia, ib, width, outw + c * width);
+        else build_mul(&pr, ia, ib, width, outw + c * width);
+    }
+    uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
+    memcpy(wires, A, count * width * W * sizeof(uint32_t));
+    memcpy(wires + count * width * W, B, count * width * W * sizeof(uint32_t));
+    run_prog(K, &pr, wires, threads);
+    for (size_t q = 0; q < count * (size_t)width; q++)
+        memcpy(R + q * W, wires + (size_t)outw[q] * W, W * sizeof(uint32_t));
+    free(wires);
+    free(outw);
+    free(ia);
+    free(ib);
+    free(pr.g);
+}
+
+void or_circuit_add(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                    size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_ADD, A, B, R, count, width, threads);
+}
+
+void or_circuit_mul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                    size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_MUL, A, B, R, count, width, threads);
+}
+
+/* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the multiplier above,
+ * each row's products summed by the tree above. */
+static void build_matvec(or_prog* pr, int32_t rows, int32_t cols, int32_t w, long* yw) {
+    long* prods = (long*)malloc((size_t)cols * w * sizeof(long));
+    long xbase = (long)rows * cols * w;
+    for (int32_t r = 0; r < rows; r++) {
+        for (int32_t c = 0; c < cols; c++) {
+            long ia[64], ib[64];
+            for (int32_t k = 0; k < w; k++) {
+                ia[k] = ((long)r * cols + c) * w + k;
+                ib[k] = xbase + (long)c * w + k;
+            }
+            build_mul(pr, ia, ib, w, prods + (size_t)c * w);
+        }
+        build_tree_sum(pr, prods, cols, w, yw + (size_t)r * w);
+    }
+    free(prods);
+}
+
+void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
+                       int32_t rows, int32_t cols, int32_t width, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    or_prog pr = {0};
+    pr.nwires = (long)rows * cols * width + (long)cols * width;
+    long* yw = (long*)malloc((size_t)rows * width * sizeof(long));
+    build_matvec(&pr, rows, cols, width, yw);
+    uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
+    memcpy(wires, M, (size_t)rows * cols * width * W * sizeof(uint32_t));
+    memcpy(wires + (size_t)rows * cols * width * W, x, (size_t)cols * width * W * sizeof(uint32_t));
+    run_prog(K, &pr, wires, threads);
+    for (long q = 0; q < (long)rows * width; q++)
+        memcpy(y + (size_t)q * W, wires + (size_t)yw[q] * W, W * sizeof(uint32_t));
+    free(wires);
+    free(yw);
+    free(pr.g);
+}
+
+long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) {
+    or_prog pr = {0};
+    long n;
+    if (kind == KIND_MATVEC) {
+        pr.nwires = (long)rows * cols * width + (long)cols * width;
+        long* yw = (long*)malloc((size_t)rows * width * sizeof(long));
+        build_matvec(&pr, rows, cols, width, yw);
+        free(yw);
+    } else {
+        long* ia = (long*)malloc((size_t)width * sizeof(long));
+        long* ib = (long*)malloc((size_t)width * sizeof(long));
+        long* r = (long*)malloc((size_t)width * sizeof(long));
+        for (int32_t k = 0; k < width; k++) { ia[k] = k; ib[k] = width + k; }
+        pr.nwires = 2L * width;
+        if (kind == KIND_ADD) build_add(&pr, ia, ib, width, r);
+        else build_mul(&pr, ia, ib, width, r);
+        free(ia);
+        free(ib);
+        free(r);
+    }
+    n = pr.ng;
+    free(pr.g);
+    return n;
+}

@@ -1,0 +1,165 @@
+"""Pins of the oracle's whole bootstrap: truth tables, special-case keys whose
+output phase has a closed form, measured noise against the variance bound,
+and circuits that must decrypt to plaintext arithmetic."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+M32 = 1 << 32
+MU = oracle.MU
+
+TRUTH = {
+    oracle.AND: lambda a, b: a & b, oracle.NAND: lambda a, b: 1 - (a & b),
+    oracle.OR: lambda a, b: a | b, oracle.NOR: lambda a, b: 1 - (a | b),
+    oracle.XOR: lambda a, b: a ^ b, oracle.XNOR: lambda a, b: 1 - (a ^ b),
+    oracle.ANDNY: lambda a, b: (1 - a) & b, oracle.ANDYN: lambda a, b: a & (1 - b),
+    oracle.ORNY: lambda a, b: (1 - a) | b, oracle.ORYN: lambda a, b: a | (1 - b),
+}
+
+
+def signed(x):
+    x = int(x) % M32
+    return x - M32 if x >= M32 // 2 else x
+
+
+def test_truth_tables_all_gates(okeys):
+    a_bits, b_bits = workloads.truth_table_inputs()
+    ops, A, B, want = [], [], [], []
+    for op in range(10):
+        for a, b in zip(a_bits, b_bits):
+            ops.append(op)
+            A.append(a)
+            B.append(b)
+            want.append(TRUTH[op](int(a), int(b)))
+    ca = okeys.encrypt_bits(A, nonce=10_000)
+    cb = okeys.encrypt_bits(B, nonce=20_000)
+    out = okeys.bootstrap(ops, ca, cb)
+    assert list(okeys.decrypt_bits(out)) == want
+    # output phase is +-mu up to the bootstrap noise (sigma ~ 3.6e-3 << 1/16)
+    ph = okeys.phase(out).astype(np.int64)
+    err = np.abs(ph - np.where(np.array(want) == 1, MU, -MU)) / M32
+    assert err.max() < 1 / 32
+
+
+def test_zero_key_noiseless_closed_form():
+    """LWE key s = 0 and noiseless keys: every BK_i is a noiseless TGSW(0), so
+    the accumulator phase stays exactly X^(-bbar) v and the extracted phase is
+    +mu iff bbar < N, else -mu, with no error at all.  After key switching with
+    noiseless KSK under s = 0 the output body is exactly
+    b' - sum_i S_i round16(a'_i)."""
+    P = oracle.default_params(lwe_stdev=0.0, bk_stdev=0.0)
+    K = oracle.Keys(seed=3, params=P, lwe_key=np.zeros(P.n, np.int32))
+    g = np.random.default_rng(5)
+    for trial in range(3):
+        lwe = g.integers(0, M32, P.n + 1, dtype=np.uint64).astype(np.uint32)
+        acc = K.blind_rotate(lwe)
+        big = K.sample_extract(acc)
+        S = K.tlwe_key.astype(np.int64)
+        ph = (int(big[-1]) - int((big[:-1].astype(np.int64) * S).sum())) % M32
+        bbar = oracle.modswitch(int(lwe[-1]), P)
+        assert ph == (MU if bbar < P.N else M32 - MU)
+        out = K.key_switch(big)
+        rounded = (((big[:-1].astype(np.int64) + (1 << 15)) >> 16) << 16) % M32
+        want = (int(big[-1]) - int((S * rounded).sum())) % M32
+        assert int(out[-1]) == want
+
+
+def test_single_key_bit_rotation_direction():
+    """s = e_i0 with noiseless keys: only CMux i0 rotates, so the extracted
+    phase is +mu iff (bbar - abar_i0) mod 2N < N (up to the gadget rounding
+    error, at most 2^11 (1 + N) << mu)."""
+    P = oracle.default_params(lwe_stdev=0.0, bk_stdev=0.0)
+    i0 = 137
+    key = np.zeros(P.n, np.int32)
+    key[i0] = 1
+    K = oracle.Keys(seed=4, params=P, lwe_key=key)
+    g = np.random.default_rng(9)
+    S = K.tlwe_key.astype(np.int64)
+    for trial in range(3):
+        lwe = g.integers(0, M32, P.n + 1, dtype=np.uint64).astype(np.uint32)
+        acc = K.blind_rotate(lwe)
+        big = K.sample_extract(acc)
+        ph = signed(int(big[-1]) - int((big[:-1].astype(np.int64) * S).sum()))
+        bbar = oracle.modswitch(int(lwe[-1]), P)
+        abar = oracle.modswitch(int(lwe[i0]), P)
+        sign = 1 if (bbar - abar) % (2 * P.N) < P.N else -1
+        assert abs(ph - sign * MU) <= (1 << 11) * (1 + P.N)
+
+
+def test_cmux_with_trivial_key_rotates_exactly():
+    """A CMux whose key row set is the gadget matrix itself (a noiseless
+    trivial TGSW(1)) replaces acc by X^abar acc up to the decomposition error
+    of at most 2^11 per coefficient."""
+    P = oracle.default_params()
+    N = P.N
+    bk = np.zeros((4, 2, N), np.uint32)
+    for j in range(2):
+        for p in range(2):
+            bk[2 * j + p, j, 0] = 1 << (32 - 10 * (p + 1))
+    g = np.random.default_rng(12)
+    acc = g.integers(0, M32, 2 * N, dtype=np.uint64).astype(np.uint32)
+    for abar in (0, 1, 777, 1024, 2047):
+        out = oracle.cmux(bk, abar, acc, P)
+        want = np.concatenate([oracle.rotate(acc[:N], abar), oracle.rotate(acc[N:], abar)])
+        d = (out.astype(np.int64) - want.astype(np.int64)) % M32
+        d = np.where(d >= M32 // 2, d - M32, d)
+        assert np.abs(d).max() <= 1 << 11
+
+
+def test_bootstrap_noise_within_bound(okeys):
+    """Output-noise variance is below the worst-case bound 3.27e-5 and near the
+    average-case estimate 1.29e-5 (sample of 64 bootstraps: loose band)."""
+    count = 64
+    g = np.random.default_rng(21)
+    a = g.integers(0, 2, count, dtype=np.uint8)
+    b = g.integers(0, 2, count, dtype=np.uint8)
+    out = okeys.bootstrap([oracle.AND] * count, okeys.encrypt_bits(a, nonce=30_000),
+                          okeys.encrypt_bits(b, nonce=40_000))
+    want = a & b
+    ph = okeys.phase(out).astype(np.int64)
+    err = (ph - np.where(want == 1, MU, -MU)) / M32
+    var = float(np.mean(err ** 2))
+    assert var < 3.27e-5
+    assert 0.45 * 1.29e-5 < var < 1.9 * 1.29e-5
+
+
+def test_add_circuit_decrypts_to_sum(okeys):
+    w = 4
+    a = np.array([9, 15], np.uint64)
+    b = np.array([8, 3], np.uint64)
+    R = okeys.add(okeys.encrypt_uint(a, w, nonce=50_000), okeys.encrypt_uint(b, w, nonce=60_000), w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a + b) % (1 << w))
+
+
+def test_mul_circuit_decrypts_to_low_product(okeys):
+    w = 4
+    a = np.array([13], np.uint64)
+    b = np.array([11], np.uint64)
+    R = okeys.mul(okeys.encrypt_uint(a, w, nonce=70_000), okeys.encrypt_uint(b, w, nonce=80_000), w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a * b) % (1 << w))
+
+
+def test_matvec_circuit_decrypts_to_product(okeys):
+    w, rows, cols = 2, 2, 2
+    M = np.array([[3, 2], [1, 3]], np.uint64)
+    x = np.array([3, 1], np.uint64)
+    cm = okeys.encrypt_uint(M.reshape(-1), w, nonce=90_000)
+    cx = okeys.encrypt_uint(x, w, nonce=95_000)
+    y = okeys.matvec(cm, cx, rows, cols, w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(y, w), (M @ x) % (1 << w))
+
+
+def test_circuit_gate_counts():
+    """Gate counts of the circuit definitions: w-bit ripple-carry adder
+    5w - 6, shift-and-add multiplier, and the 64x64 16-bit matvec."""
+    assert oracle.circuit_gate_count("add", 16) == 74
+    assert oracle.circuit_gate_count("add", 32) == 154
+    for w in range(2, 40):
+        assert oracle.circuit_gate_count("add", w) == 5 * w - 6
+    ands = 32 * 33 // 2
+    adders = 1 + sum(5 * m - 6 for m in range(2, 32))
+    assert oracle.circuit_gate_count("mul", 32) == ands + adders == 2824
+    assert oracle.circuit_gate_count("mul", 16) == 648
+    assert oracle.circuit_gate_count("matvec", 16, 64, 64) == 4096 * 648 + 64 * 63 * 74

@@ -1,0 +1,146 @@
+"""Pins of the oracle's generator, decomposition, modulus switch and gate
+constants against published values and exact rational arithmetic."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+M32 = 1 << 32
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def test_splitmix64_published_sequence():
+    """SplitMix64 from state 0 (Steele, Lea, Flood, OOPSLA 2014): the first
+    three outputs of the reference generator; the fixture cites the source."""
+    vals = []
+    with open(f"{GOLDEN}/splitmix64_seed0.txt") as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                vals.append(int(line, 16))
+    gamma = 0x9E3779B97F4A7C15
+    for k, want in enumerate(vals):
+        assert oracle.mix64((gamma * (k + 1)) % (1 << 64)) == want
+
+
+def test_gaussian_moments_and_torus_rounding():
+    z = np.array([oracle.gaussian(5, 4, i) for i in range(40000)])
+    assert abs(z.mean()) < 0.03
+    assert abs(z.var() - 1.0) < 0.04
+    assert abs(np.mean(np.abs(z) < 1.0) - 0.6827) < 0.01
+    assert oracle.torus_from_double(0.25) == 1 << 30
+    assert oracle.torus_from_double(-0.25) == M32 - (1 << 30)
+    assert oracle.torus_from_double(0.5 / M32) == 0          # tie -> even
+    assert oracle.torus_from_double(1.5 / M32) == 2
+    assert oracle.torus_from_double(-1.0 / M32) == M32 - 1
+
+
+def _decomp_check(xs, P):
+    l, bg = P.bk_l, P.bk_bgbit
+    for x in xs:
+        d = oracle.gadget_decompose(int(x), P)
+        assert all(-(1 << (bg - 1)) <= v < (1 << (bg - 1)) for v in d)
+        rec = sum(int(v) << (32 - bg * (p + 1)) for p, v in enumerate(d))
+        err = (int(x) - rec) % M32
+        err = err - M32 if err >= M32 // 2 else err
+        assert abs(err) <= 1 << (32 - l * bg - 1), (x, d, err)
+
+
+def test_gadget_decomposition_error_and_range():
+    """x ~= sum_p d_p 2^(32-10(p+1)) with d_p in [-512, 511] and |error| <=
+    2^11, on every rounding boundary of the low 12 bits and a random sample."""
+    P = oracle.default_params()
+    g = np.random.default_rng(0)
+    xs = list(g.integers(0, M32, 3000, dtype=np.uint64))
+    for hi in list(range(0, 1 << 20, 4099)) + [0, (1 << 20) - 1, 1 << 19, (1 << 19) - 1]:
+        for lo in (0, 1, (1 << 11) - 1, 1 << 11, (1 << 11) + 1, (1 << 12) - 1):
+            xs.append((hi << 12) | lo)
+    _decomp_check(xs, P)
+
+
+def test_gadget_decomposition_ties_round_up():
+    P = oracle.default_params()
+    # low 12 bits exactly 2^11: rounds up to the next multiple of 2^12
+    x = (5 << 12) | (1 << 11)
+    d = oracle.gadget_decompose(x, P)
+    rec = sum(int(v) << (32 - 10 * (p + 1)) for p, v in enumerate(d)) % M32
+    assert rec == 6 << 12
+    assert list(oracle.gadget_decompose(0, P)) == [0, 0]
+
+
+def test_modswitch_is_round_to_nearest_mod_2n():
+    P = oracle.default_params()
+    g = np.random.default_rng(1)
+    xs = list(g.integers(0, M32, 2000, dtype=np.uint64))
+    xs += [0, 1, (1 << 20) - 1, 1 << 20, (1 << 20) + 1, M32 - 1, M32 - (1 << 20), M32 - (1 << 20) - 1]
+    for x in xs:
+        q = Fraction(int(x) * 2048, M32)
+        want = math.floor(q + Fraction(1, 2)) % 2048   # ties up, wrap mod 2N
+        assert oracle.modswitch(int(x), P) == want
+
+
+@pytest.mark.parametrize("op", range(10))
+def test_gate_constants_put_truth_in_positive_half(op):
+    """For noiseless +-mu inputs the combined phase lies in (0, 1/2) exactly when
+    the gate's truth value is 1, with margin at least 1/8."""
+    truth = {
+        oracle.AND: lambda a, b: a & b, oracle.NAND: lambda a, b: 1 - (a & b),
+        oracle.OR: lambda a, b: a | b, oracle.NOR: lambda a, b: 1 - (a | b),
+        oracle.XOR: lambda a, b: a ^ b, oracle.XNOR: lambda a, b: 1 - (a ^ b),
+        oracle.ANDNY: lambda a, b: (1 - a) & b, oracle.ANDYN: lambda a, b: a & (1 - b),
+        oracle.ORNY: lambda a, b: (1 - a) | b, oracle.ORYN: lambda a, b: a | (1 - b),
+    }[op]
+    P = oracle.default_params()
+    mu = oracle.MU
+    for a in (0, 1):
+        for b in (0, 1):
+            c1 = np.zeros(P.n + 1, np.uint32)
+            c2 = np.zeros(P.n + 1, np.uint32)
+            c1[-1] = mu if a else M32 - mu
+            c2[-1] = mu if b else M32 - mu
+            ph = int(oracle.gate_combine(op, c1, c2, P)[-1])
+            ph = ph - M32 if ph >= M32 // 2 else ph
+            frac = Fraction(ph, M32)
+            if truth(a, b):
+                assert Fraction(1, 8) <= frac <= Fraction(3, 8)
+            else:
+                assert Fraction(-3, 8) <= frac <= Fraction(-1, 8)
+
+
+def test_fresh_encryption_noise(okeys):
+    g = np.random.default_rng(2)
+    bits = g.integers(0, 2, 20000, dtype=np.uint8)
+    ct = okeys.encrypt_bits(bits, nonce=1 << 40)
+    ph = okeys.phase(ct).astype(np.int64)
+    err = (ph - np.where(bits == 1, oracle.MU, -oracle.MU)) / M32
+    sigma = okeys.P.lwe_stdev
+    assert abs(err.std() / sigma - 1.0) < 0.03
+    assert np.array_equal(okeys.decrypt_bits(ct), bits)
+
+
+def test_key_shapes_and_zero_ksk_rows(okeys):
+    P = okeys.P
+    assert okeys.bk.shape == (P.n, 4, 2, P.N)
+    assert okeys.ksk.shape == (P.N, P.ks_t, 4, P.n + 1)
+    assert not okeys.ksk[:, :, 0, :].any()
+    # keys are binary with about half ones
+    assert set(np.unique(okeys.lwe_key)) <= {0, 1}
+    assert 200 < okeys.lwe_key.sum() < 300
+    assert 412 < okeys.tlwe_key.sum() < 612
+
+
+def test_ksk_rows_decrypt_to_scaled_key_bits(okeys):
+    """KSK[i][j][v] encrypts v * s'_i * 2^(32-2(j+1)) under the LWE key."""
+    P = okeys.P
+    for i in (0, 1, 511, 1023):
+        for j in (0, 3, 7):
+            for v in (1, 2, 3):
+                row = okeys.ksk[i, j, v]
+                ph = okeys.phase(row)[0]
+                want = (v * int(okeys.tlwe_key[i]) << (32 - 2 * (j + 1))) % M32
+                err = (int(ph) - want) % M32
+                err = err - M32 if err >= M32 // 2 else err
+                assert abs(err) < 8 * P.lwe_stdev * M32
