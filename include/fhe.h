@@ -1,0 +1,219 @@
+/*
+ * fhe.h — C ABI of the MI355X (gfx950) TFHE gate-bootstrapping library.
+ *
+ * The library evaluates boolean gates on LWE-encrypted bits with one
+ * bootstrap per gate (paper Sec. II-A: bootstrapping decrypts and re-encrypts
+ * under encryption to reset the noise; Fig. 2: a gate runs its linear
+ * combination, bootstrapping with the BS key, then key switching with the KS
+ * key), and builds the paper's integer circuits from those gates (Sec. III
+ * and V-B: ripple-carry addition, shift-and-add multiplication, vector and
+ * matrix products with tree accumulation).
+ *
+ * Conventions
+ *  - Every function returns int: FHE_OK (0) or a negative FHE_E* code.  No
+ *    C++ exception and no abort crosses this boundary.  fhe_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Torus32: a uint32 word w stands for w / 2^32 on the torus R/Z.
+ *  - An LWE ciphertext is n+1 uint32 words laid out a[0..n-1], b.  A batch of
+ *    `count` ciphertexts is contiguous, [count][n+1] (the paper's bit
+ *    coalescing, Sec. V-A-2).  An encrypted w-bit integer is w consecutive
+ *    ciphertexts, least significant bit first.
+ *  - A bit is encrypted as +1/8 (bit 1) or -1/8 (bit 0) plus Gaussian noise;
+ *    decryption returns 1 when the phase b - <a, s>, read as a signed int32,
+ *    is > 0.
+ *  - Handles (fhe_secret_key, fhe_cloud_key, fhe_ctx, fhe_server) are
+ *    allocated and freed by the library.  Ciphertext buffers are always owned
+ *    by the caller; the library never frees or retains them beyond the
+ *    completion of the work it enqueued on the caller's stream.
+ *  - Functions taking `void* stream` read and write DEVICE memory (for
+ *    example torch tensors' data_ptr()) and are asynchronous on that HIP
+ *    stream (NULL = the default stream).  They return once the work is
+ *    enqueued.  Functions without a stream take HOST buffers and complete
+ *    before returning.
+ *  - Inputs and outputs of one call must not overlap.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef FHE_H
+#define FHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FHE_OK = 0,
+    FHE_EINVAL = -1,     /* bad argument (null pointer, size, parameter set) */
+    FHE_ENOMEM = -2,     /* host or device allocation failed */
+    FHE_EDEVICE = -3,    /* HIP runtime error, or no usable gfx950 device */
+    FHE_EBUSY = -4,      /* a serving job does not fit the HBM budget now */
+    FHE_ECANCELED = -5,  /* a serving job was cancelled */
+    FHE_EIO = -6         /* key file could not be read or written */
+};
+
+/* TFHE parameters.  The library's kernels are specialised for the 110-bit
+ * gate-bootstrapping set the paper uses (Sec. VII: "analogous to the
+ * existing implementation of TFHE"): n=500, N=1024, k=1, l=2, Bgbit=10, t=8,
+ * basebit=2.  Any other structural value is rejected with FHE_EINVAL; the
+ * noise deviations may be changed (0 gives noiseless keys for tests). */
+typedef struct {
+    uint32_t n;          /* LWE dimension */
+    uint32_t N;          /* ring degree of Z/2^32[X]/(X^N+1) */
+    uint32_t k;          /* TLWE mask polynomials (1) */
+    uint32_t bk_l;       /* gadget digits */
+    uint32_t bk_bgbit;   /* bits per gadget digit */
+    uint32_t ks_t;       /* key-switch digits */
+    uint32_t ks_basebit; /* bits per key-switch digit */
+    double lwe_stdev;    /* noise of fresh ciphertexts and of the KS key */
+    double bk_stdev;     /* noise of the bootstrapping key */
+} fhe_params;
+
+typedef struct fhe_secret_key fhe_secret_key; /* host-only */
+typedef struct fhe_cloud_key fhe_cloud_key;   /* host copy of BK and KSK */
+typedef struct fhe_ctx fhe_ctx;               /* device-resident keys on one GPU */
+
+/* Gate codes, one byte each on the wire.  NY / YN negate the first / second
+ * input (ANDNY = (not a) and b). */
+typedef enum {
+    FHE_AND = 0, FHE_NAND = 1, FHE_OR = 2, FHE_NOR = 3, FHE_XOR = 4, FHE_XNOR = 5,
+    FHE_ANDNY = 6, FHE_ANDYN = 7, FHE_ORNY = 8, FHE_ORYN = 9
+} fhe_gate;
+
+/* ---------------------------------------------------------------------- */
+/* Parameters and keys (host).                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Fills *out with the default parameter set above. */
+int fhe_default_params(fhe_params* out);
+
+/* Generates a secret key and the matching cloud key (bootstrapping key =
+ * TGSW encryptions of the LWE key bits under the TLWE key; key-switching key
+ * = LWE encryptions of the TLWE key bits scaled by each base-4 digit
+ * position).  All randomness comes from the counter-based generator keyed by
+ * `seed`, so the same seed gives the same key bytes.  *sk and *ck receive new
+ * handles; free them with fhe_secret_key_free / fhe_cloud_key_free. */
+int fhe_keygen(const fhe_params* params, uint64_t seed, fhe_secret_key** sk,
+               fhe_cloud_key** ck);
+
+/* As fhe_keygen, but the binary keys are given instead of drawn: lwe_key has
+ * n entries and tlwe_key N entries, each 0 or 1; either may be NULL to draw
+ * it from the seed.  Used for special-case keys with known outputs. */
+int fhe_keygen_with_keys(const fhe_params* params, uint64_t seed, const int32_t* lwe_key,
+                         const int32_t* tlwe_key, fhe_secret_key** sk, fhe_cloud_key** ck);
+
+void fhe_secret_key_free(fhe_secret_key* sk);
+void fhe_cloud_key_free(fhe_cloud_key* ck);
+
+/* Copies key material out (host buffers, any may be NULL):
+ *   lwe_key [n], tlwe_key [N]                        int32 in {0,1}
+ *   bk  [n][2l][2][N]  uint32, row r = 2j + p, column c
+ *   ksk [N][t][2^basebit][n+1] uint32 (value-0 rows are all zero) */
+int fhe_secret_key_export(const fhe_secret_key* sk, int32_t* lwe_key, int32_t* tlwe_key);
+int fhe_cloud_key_export(const fhe_cloud_key* ck, uint32_t* bk, uint32_t* ksk);
+int fhe_cloud_key_params(const fhe_cloud_key* ck, fhe_params* out);
+
+/* Saves both keys to one file / loads them back (checkpoint of key state).
+ * Either handle may be NULL on save; on load, absent parts come back NULL.
+ * Errors: FHE_EIO on file errors or a malformed file. */
+int fhe_key_save(const fhe_secret_key* sk, const fhe_cloud_key* ck, const char* path);
+int fhe_key_load(const char* path, fhe_secret_key** sk, fhe_cloud_key** ck);
+
+/* ---------------------------------------------------------------------- */
+/* Encryption and decryption (host buffers; paper Sec. II-A).               */
+/* ---------------------------------------------------------------------- */
+
+/* Encrypts count bits (each 0 or 1) into ct_out[count][n+1].  Ciphertext c
+ * uses randomness index nonce + c: never reuse a nonce range under one key. */
+int fhe_encrypt_bits(const fhe_secret_key* sk, const uint8_t* bits, size_t count,
+                     uint64_t nonce, uint32_t* ct_out);
+
+/* Encrypts count integers of `width` bits (1..64; higher bits ignored) into
+ * ct_out[count][width][n+1], LSB first; bit k of integer c uses randomness
+ * index nonce + c*width + k. */
+int fhe_encrypt_uint(const fhe_secret_key* sk, const uint64_t* v, size_t count,
+                     uint32_t width, uint64_t nonce, uint32_t* ct_out);
+
+int fhe_decrypt_bits(const fhe_secret_key* sk, const uint32_t* ct, size_t count,
+                     uint8_t* bits_out);
+int fhe_decrypt_uint(const fhe_secret_key* sk, const uint32_t* ct, size_t count,
+                     uint32_t width, uint64_t* v_out);
+
+/* Phase b - <a, s> of each ciphertext as a signed int32 (noise tests). */
+int fhe_phase(const fhe_secret_key* sk, const uint32_t* ct, size_t count, int32_t* phase_out);
+
+/* ---------------------------------------------------------------------- */
+/* Device context.                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Uploads the cloud key to HIP device `device`, converts the bootstrapping
+ * key to the NTT domain over p = 2^64 - 2^32 + 1 (32.8 MB) and lays out the
+ * key-switching key for row gathers (50.3 MB).  The cloud key may be freed
+ * afterwards.  Errors: FHE_EDEVICE if the device is missing or not gfx950. */
+int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out);
+void fhe_ctx_destroy(fhe_ctx* ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Gate bootstrapping (device buffers, asynchronous on `stream`).           */
+/* ---------------------------------------------------------------------- */
+
+/* out[g] = gate ops[g] applied to (in0[g], in1[g]) for g < count: linear
+ * combination, modulus switch, 500-step CMux blind rotation of the test
+ * vector, sample extraction and key switching, all gates of the batch in one
+ * launch per step.  ops: device uint8[count]; in0, in1, out: device
+ * uint32[count][n+1].  count = 0 is a no-op.  The result is bit-exact with
+ * the definition (exact NTT arithmetic). */
+int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0,
+                             const uint32_t* in1, uint32_t* out, size_t count, void* stream);
+
+/* One gate per launch, synchronous: enqueues one bootstrap on `stream` and
+ * waits for it.  The baseline for batched throughput. */
+int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
+                             const uint32_t* in1, uint32_t* out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Circuits on encrypted integers (device buffers, asynchronous).           */
+/* Each circuit level runs as one batched launch over every gate of the     */
+/* level (all `count` instances together).                                   */
+/* ---------------------------------------------------------------------- */
+
+/* R = (A + B) mod 2^width, ripple-carry adder of eqs. (1)-(2).
+ * A, B, R: device uint32[count][width][n+1]; width 1..64. */
+int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+            uint32_t width, void* stream);
+
+/* R = (A * B) mod 2^width, shift-and-add multiplier (Sec. III-B-1) keeping the
+ * low width bits. */
+int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+            uint32_t width, void* stream);
+
+/* y = M x mod 2^width: every product by the multiplier above, each row summed
+ * by a tree of adders (Sec. V-B-2, Fig. 4: split in halves, add pairwise).
+ * M: device uint32[rows][cols][width][n+1]; x: [cols][width][n+1];
+ * y: [rows][width][n+1]. */
+int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
+               uint32_t cols, uint32_t width, void* stream);
+
+/* Number of gates and of levels of a circuit as the library schedules it
+ * (kind 0 = add, 1 = mul, 2 = matvec; rows/cols only for matvec). */
+int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
+                      uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
+
+/* ---------------------------------------------------------------------- */
+/* Errors and diagnostics.                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* fhe_last_error(void);
+
+/* Test entry: one CMux step of the blind rotation on explicit HOST data,
+ * computed on `device` with the production NTT path:
+ *   acc[2][N] <- acc + BK_i [x] (X^abar acc - acc),
+ * bk_i: uint32 [2l][2][N] (coefficient domain, rows r = 2j + p). */
+int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, uint32_t* acc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

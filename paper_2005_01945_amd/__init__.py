@@ -1,0 +1,297 @@
+"""Thin Python binding of libfhe_mi355x.so (include/fhe.h).
+
+Argument marshalling only: every step of gate bootstrapping runs in the HIP
+kernels of the library.  Functions named fhe_* mirror the C ABI one to one;
+device buffers are torch tensors (their data_ptr()), streams are torch
+streams.  Importing never falls back to anything: if the library is not built
+the first call raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhe_mi355x.so")
+
+FHE_OK, FHE_EINVAL, FHE_ENOMEM, FHE_EDEVICE, FHE_EBUSY, FHE_ECANCELED, FHE_EIO = 0, -1, -2, -3, -4, -5, -6
+AND, NAND, OR, NOR, XOR, XNOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
+WORDS = 501  # n + 1 words per LWE sample
+
+
+class FheError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class fhe_params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("N", C.c_uint32), ("k", C.c_uint32), ("bk_l", C.c_uint32),
+                ("bk_bgbit", C.c_uint32), ("ks_t", C.c_uint32), ("ks_basebit", C.c_uint32),
+                ("lwe_stdev", C.c_double), ("bk_stdev", C.c_double)]
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "fhe_default_params": (C.c_int, [C.POINTER(fhe_params)]),
+    "fhe_keygen": (C.c_int, [C.POINTER(fhe_params), C.c_uint64, C.POINTER(_vp), C.POINTER(_vp)]),
+    "fhe_keygen_with_keys": (C.c_int, [C.POINTER(fhe_params), C.c_uint64, _vp, _vp, C.POINTER(_vp), C.POINTER(_vp)]),
+    "fhe_secret_key_free": (None, [_vp]),
+    "fhe_cloud_key_free": (None, [_vp]),
+    "fhe_secret_key_export": (C.c_int, [_vp, _vp, _vp]),
+    "fhe_cloud_key_export": (C.c_int, [_vp, _vp, _vp]),
+    "fhe_cloud_key_params": (C.c_int, [_vp, C.POINTER(fhe_params)]),
+    "fhe_key_save": (C.c_int, [_vp, _vp, C.c_char_p]),
+    "fhe_key_load": (C.c_int, [C.c_char_p, C.POINTER(_vp), C.POINTER(_vp)]),
+    "fhe_encrypt_bits": (C.c_int, [_vp, _vp, C.c_size_t, C.c_uint64, _vp]),
+    "fhe_encrypt_uint": (C.c_int, [_vp, _vp, C.c_size_t, C.c_uint32, C.c_uint64, _vp]),
+    "fhe_decrypt_bits": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "fhe_decrypt_uint": (C.c_int, [_vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_phase": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "fhe_ctx_create": (C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
+    "fhe_ctx_destroy": (None, [_vp]),
+    "fhe_bootstrap_gate_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_bootstrap_gate_plain": (C.c_int, [_vp, C.c_uint8, _vp, _vp, _vp, _vp]),
+    "fhe_add": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_mul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
+    "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
+                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
+    "fhe_last_error": (C.c_char_p, []),
+    "fhe_debug_cmux": (C.c_int, [C.c_int, _vp, C.c_int32, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded C library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FheError(FHE_EDEVICE, f"{LIB_PATH} is not built (python -m paper_2005_01945_amd.build)")
+        # torch bundles its own HIP runtime with the same soname as the system
+        # one; loading torch first makes the library bind to that single copy
+        # (two HIP runtimes in one process cannot share device memory).
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc, name):
+    if rc != FHE_OK:
+        raise FheError(rc, f"{name}: {lib().fhe_last_error().decode()}")
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def _dev(t):
+    """Device pointer of a contiguous torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+# ---------------------------------------------------------------------------
+# Same-named wrappers of the C ABI.
+# ---------------------------------------------------------------------------
+
+def fhe_default_params() -> fhe_params:
+    P = fhe_params()
+    _check(lib().fhe_default_params(C.byref(P)), "fhe_default_params")
+    return P
+
+
+class SecretKey:
+    def __init__(self, handle, params):
+        self.h, self.P = handle, params
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fhe_secret_key_free(self.h)
+            self.h = None
+
+    def export(self):
+        lwe = np.empty(self.P.n, np.int32)
+        tlwe = np.empty(self.P.N, np.int32)
+        _check(lib().fhe_secret_key_export(self.h, lwe.ctypes.data, tlwe.ctypes.data), "fhe_secret_key_export")
+        return lwe, tlwe
+
+    def encrypt_bits(self, bits, nonce=0):
+        b, pb = _host(bits, np.uint8)
+        out = np.empty((b.size, WORDS), np.uint32)
+        _check(lib().fhe_encrypt_bits(self.h, pb, b.size, nonce, out.ctypes.data), "fhe_encrypt_bits")
+        return out
+
+    def encrypt_uint(self, values, width, nonce=0):
+        v, pv = _host(np.asarray(values).reshape(-1), np.uint64)
+        out = np.empty((v.size, width, WORDS), np.uint32)
+        _check(lib().fhe_encrypt_uint(self.h, pv, v.size, width, nonce, out.ctypes.data), "fhe_encrypt_uint")
+        return out
+
+    def decrypt_bits(self, ct):
+        c, pc = _host(np.asarray(ct).reshape(-1, WORDS), np.uint32)
+        out = np.empty(c.shape[0], np.uint8)
+        _check(lib().fhe_decrypt_bits(self.h, pc, c.shape[0], out.ctypes.data), "fhe_decrypt_bits")
+        return out
+
+    def decrypt_uint(self, ct, width):
+        c, pc = _host(np.asarray(ct).reshape(-1, WORDS), np.uint32)
+        count = c.shape[0] // width
+        out = np.empty(count, np.uint64)
+        _check(lib().fhe_decrypt_uint(self.h, pc, count, width, out.ctypes.data), "fhe_decrypt_uint")
+        return out
+
+    def phase(self, ct):
+        c, pc = _host(np.asarray(ct).reshape(-1, WORDS), np.uint32)
+        out = np.empty(c.shape[0], np.int32)
+        _check(lib().fhe_phase(self.h, pc, c.shape[0], out.ctypes.data), "fhe_phase")
+        return out
+
+
+class CloudKey:
+    def __init__(self, handle, params):
+        self.h, self.P = handle, params
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fhe_cloud_key_free(self.h)
+            self.h = None
+
+    def export(self):
+        P = self.P
+        bk = np.empty((P.n, 4, 2, P.N), np.uint32)
+        ksk = np.empty((P.N, P.ks_t, 1 << P.ks_basebit, P.n + 1), np.uint32)
+        _check(lib().fhe_cloud_key_export(self.h, bk.ctypes.data, ksk.ctypes.data), "fhe_cloud_key_export")
+        return bk, ksk
+
+
+def fhe_keygen(seed=0, params=None, lwe_key=None, tlwe_key=None):
+    """(SecretKey, CloudKey) from the counter-based generator keyed by seed."""
+    P = params if params is not None else fhe_default_params()
+    sk, ck = _vp(), _vp()
+    if lwe_key is None and tlwe_key is None:
+        rc = lib().fhe_keygen(C.byref(P), seed, C.byref(sk), C.byref(ck))
+    else:
+        lk = None if lwe_key is None else np.ascontiguousarray(lwe_key, np.int32)
+        tk = None if tlwe_key is None else np.ascontiguousarray(tlwe_key, np.int32)
+        rc = lib().fhe_keygen_with_keys(C.byref(P), seed, None if lk is None else lk.ctypes.data,
+                                        None if tk is None else tk.ctypes.data, C.byref(sk), C.byref(ck))
+    _check(rc, "fhe_keygen")
+    return SecretKey(sk.value, P), CloudKey(ck.value, P)
+
+
+def fhe_key_save(sk, ck, path):
+    _check(lib().fhe_key_save(sk.h if sk else None, ck.h if ck else None, path.encode()), "fhe_key_save")
+
+
+def fhe_key_load(path):
+    sk, ck = _vp(), _vp()
+    _check(lib().fhe_key_load(path.encode(), C.byref(sk), C.byref(ck)), "fhe_key_load")
+    P = fhe_default_params()
+    if ck.value:
+        _check(lib().fhe_cloud_key_params(ck.value, C.byref(P)), "fhe_cloud_key_params")
+    return (SecretKey(sk.value, P) if sk.value else None), (CloudKey(ck.value, P) if ck.value else None)
+
+
+class Context:
+    """Device-resident keys on one GPU (fhe_ctx)."""
+
+    def __init__(self, cloud_key, device=0):
+        h = _vp()
+        _check(lib().fhe_ctx_create(cloud_key.h, device, C.byref(h)), "fhe_ctx_create")
+        self.h, self.device = h.value, device
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fhe_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def fhe_bootstrap_gate_batch(ctx, ops, in0, in1, out, count=None, stream=None):
+    count = ops.numel() if count is None else count
+    _check(lib().fhe_bootstrap_gate_batch(ctx.h, _dev(ops), _dev(in0), _dev(in1), _dev(out), count,
+                                          _stream(stream)), "fhe_bootstrap_gate_batch")
+
+
+def fhe_bootstrap_gate_plain(ctx, op, in0, in1, out, stream=None):
+    _check(lib().fhe_bootstrap_gate_plain(ctx.h, op, _dev(in0), _dev(in1), _dev(out), _stream(stream)),
+           "fhe_bootstrap_gate_plain")
+
+
+def fhe_add(ctx, A, B, R, count, width, stream=None):
+    _check(lib().fhe_add(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_add")
+
+
+def fhe_mul(ctx, A, B, R, count, width, stream=None):
+    _check(lib().fhe_mul(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_mul")
+
+
+def fhe_matvec(ctx, M, x, y, rows, cols, width, stream=None):
+    _check(lib().fhe_matvec(ctx.h, _dev(M), _dev(x), _dev(y), rows, cols, width, _stream(stream)),
+           "fhe_matvec")
+
+
+def fhe_circuit_shape(kind, width, rows=0, cols=0):
+    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec'}."""
+    k = {"add": 0, "mul": 1, "matvec": 2}[kind]
+    g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
+    _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
+           "fhe_circuit_shape")
+    return g.value, lv.value, wd.value
+
+
+def fhe_debug_cmux(bk_i, abar, acc, device=0):
+    """One CMux step on host arrays with the production NTT path (test entry)."""
+    b, pb = _host(bk_i, np.uint32)
+    a = np.ascontiguousarray(acc, np.uint32).copy()
+    _check(lib().fhe_debug_cmux(device, pb, abar, a.ctypes.data), "fhe_debug_cmux")
+    return a
+
+
+# ---------------------------------------------------------------------------
+# torch helpers (plumbing: device memory only)
+# ---------------------------------------------------------------------------
+
+def to_device(arr, device="cuda:0"):
+    """Host uint32/uint8 array -> contiguous device tensor with the same bytes."""
+    import torch
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+def to_host(t):
+    """Device tensor -> numpy array (uint32 view for int32 tensors)."""
+    a = t.detach().cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a
+
+
+def empty_samples(shape, device="cuda:0"):
+    import torch
+    return torch.empty((*shape, WORDS), dtype=torch.int32, device=device)

@@ -1,0 +1,307 @@
+// Integer circuits on encrypted bits, level-scheduled onto batched gate
+// launches.
+//
+// Circuit definitions (each gate a two-input bootstrapped gate):
+//  - add, w bits, sum mod 2^w: the ripple-carry adder of eqs. (1)-(2),
+//      bit 0:     r = a^b,            c = a&b
+//      bit i:     t = a^b, g = a&b,  r = t^c, h = t&c, c = g|h
+//      bit w-1:   t = a^b,            r = t^c      (carry out dropped)
+//  - mul, low w bits: naive shift-and-add (Sec. III-B-1):
+//      acc = A & b_0;  acc[i..w-1] += (A & b_i)[0..w-1-i] for i = 1..w-1
+//  - matvec: every product by mul; each row's products accumulated by the
+//    tree of Sec. V-B-2 / Fig. 4: the list is split into first and second
+//    halves that are added element-wise, an odd last element waits a round.
+//
+// Scheduling: every gate gets its ASAP level (1 + the later of its inputs'
+// levels); all gates of one level, across all instances, run as one batched
+// launch pair (blind rotation + key switching).  Wires live in four regions:
+// the caller's two input buffers, the caller's output buffer, and a pool of
+// intermediate samples owned by the cached plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "fhe_internal.h"
+#include "runtime.h"
+
+namespace fhe {
+
+namespace {
+
+enum Kind { kAdd = 0, kMul = 1, kMatvec = 2 };
+
+struct Gate {
+    uint8_t op;
+    uint32_t in0, in1, out;
+};
+
+// One instance of a circuit over local wire ids: [0, na) first operand,
+// [na, na+nb) second operand, then one wire per gate output.
+struct Circuit {
+    uint32_t na = 0, nb = 0;
+    std::vector<Gate> gates;
+    std::vector<uint32_t> outputs;
+    uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
+};
+
+class Builder {
+  public:
+    Circuit c;
+    Builder(uint32_t na, uint32_t nb) {
+        c.na = na;
+        c.nb = nb;
+    }
+    uint32_t gate(uint8_t op, uint32_t a, uint32_t b) {
+        const uint32_t o = c.na + c.nb + (uint32_t)c.gates.size();
+        c.gates.push_back({op, a, b, o});
+        return o;
+    }
+    std::vector<uint32_t> add(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t w = a.size();
+        std::vector<uint32_t> r(w);
+        if (w == 0) return r;
+        r[0] = gate(FHE_XOR, a[0], b[0]);
+        if (w == 1) return r;
+        uint32_t carry = gate(FHE_AND, a[0], b[0]);
+        for (size_t i = 1; i < w; ++i) {
+            const uint32_t t = gate(FHE_XOR, a[i], b[i]);
+            if (i == w - 1) {
+                r[i] = gate(FHE_XOR, t, carry);
+                break;
+            }
+            const uint32_t g = gate(FHE_AND, a[i], b[i]);
+            r[i] = gate(FHE_XOR, t, carry);
+            const uint32_t h = gate(FHE_AND, t, carry);
+            carry = gate(FHE_OR, g, h);
+        }
+        return r;
+    }
+    std::vector<uint32_t> mul(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t w = a.size();
+        std::vector<uint32_t> acc(w);
+        for (size_t j = 0; j < w; ++j) acc[j] = gate(FHE_AND, a[j], b[0]);
+        for (size_t i = 1; i < w; ++i) {
+            std::vector<uint32_t> pp(w - i), hi(acc.begin() + i, acc.end());
+            for (size_t j = 0; j < w - i; ++j) pp[j] = gate(FHE_AND, a[j], b[i]);
+            const std::vector<uint32_t> s = add(hi, pp);
+            std::copy(s.begin(), s.end(), acc.begin() + i);
+        }
+        return acc;
+    }
+    std::vector<uint32_t> tree_sum(std::vector<std::vector<uint32_t>> vals) {
+        while (vals.size() > 1) {
+            const size_t h = vals.size() / 2;
+            std::vector<std::vector<uint32_t>> next;
+            for (size_t k = 0; k < h; ++k) next.push_back(add(vals[k], vals[k + h]));
+            if (vals.size() & 1) next.push_back(vals.back());
+            vals.swap(next);
+        }
+        return vals.empty() ? std::vector<uint32_t>() : vals[0];
+    }
+};
+
+std::vector<uint32_t> iota_wires(uint32_t first, uint32_t count) {
+    std::vector<uint32_t> v(count);
+    for (uint32_t k = 0; k < count; ++k) v[k] = first + k;
+    return v;
+}
+
+Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
+    if (kind == kMatvec) {
+        Builder B(rows * cols * w, cols * w);
+        for (uint32_t r = 0; r < rows; ++r) {
+            std::vector<std::vector<uint32_t>> prods;
+            for (uint32_t c = 0; c < cols; ++c)
+                prods.push_back(B.mul(iota_wires((r * cols + c) * w, w), iota_wires(rows * cols * w + c * w, w)));
+            const std::vector<uint32_t> y = B.tree_sum(prods);
+            B.c.outputs.insert(B.c.outputs.end(), y.begin(), y.end());
+        }
+        return B.c;
+    }
+    Builder B(w, w);
+    const std::vector<uint32_t> a = iota_wires(0, w), b = iota_wires(w, w);
+    B.c.outputs = kind == kAdd ? B.add(a, b) : B.mul(a, b);
+    return B.c;
+}
+
+// ASAP level of every gate (inputs are level 0).
+std::vector<uint32_t> asap_levels(const Circuit& c, uint32_t* depth) {
+    std::vector<uint32_t> lev(c.wires(), 0);
+    std::vector<uint32_t> glev(c.gates.size());
+    uint32_t d = 0;
+    for (size_t k = 0; k < c.gates.size(); ++k) {
+        const Gate& g = c.gates[k];
+        glev[k] = 1 + std::max(lev[g.in0], lev[g.in1]);
+        lev[g.out] = glev[k];
+        d = std::max(d, glev[k]);
+    }
+    *depth = d;
+    return glev;
+}
+
+}  // namespace
+
+// A scheduled, device-resident plan for (kind, width, rows, cols, count).
+struct Plan {
+    uint32_t levels = 0;
+    uint64_t gates = 0;
+    std::vector<uint32_t> level_off, level_width;  // into desc
+    uint4* desc = nullptr;                         // device descriptors
+    uint32_t* pool = nullptr;                      // intermediate samples
+    uint32_t max_width = 0;
+};
+
+struct CircuitCache {
+    std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, size_t>, Plan> plans;
+};
+
+namespace {
+
+constexpr uint32_t kRegionA = 0, kRegionB = 1, kRegionR = 2, kRegionPool = 3;
+
+uint32_t wire_id(uint32_t region, uint64_t index) { return (region << 30) | (uint32_t)index; }
+
+int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, size_t count, Plan* P) {
+    const Circuit c = build_circuit(kind, w, rows, cols);
+    uint32_t depth = 0;
+    const std::vector<uint32_t> glev = asap_levels(c, &depth);
+    const uint32_t nw = c.wires();
+    // Local wire -> (region, index within instance) for one instance.
+    std::vector<uint32_t> region(nw, kRegionPool), local(nw, 0);
+    for (uint32_t k = 0; k < c.na; ++k) { region[k] = kRegionA; local[k] = k; }
+    for (uint32_t k = 0; k < c.nb; ++k) { region[c.na + k] = kRegionB; local[c.na + k] = k; }
+    for (size_t j = 0; j < c.outputs.size(); ++j) { region[c.outputs[j]] = kRegionR; local[c.outputs[j]] = (uint32_t)j; }
+    uint32_t npool = 0;
+    for (const Gate& g : c.gates)
+        if (region[g.out] == kRegionPool) local[g.out] = npool++;
+    const uint64_t per_region[4] = {c.na, c.nb, (uint64_t)c.outputs.size(), npool};
+    for (int r = 0; r < 4; ++r)
+        if (per_region[r] * count >= (1ull << 30))
+            return set_error(FHE_EINVAL, "circuit too large for one plan (%llu samples in a region)",
+                             (unsigned long long)(per_region[r] * count));
+
+    auto gid = [&](uint32_t wl, size_t inst) {
+        return wire_id(region[wl], (uint64_t)inst * per_region[region[wl]] + local[wl]);
+    };
+    std::vector<std::vector<uint32_t>> by_level(depth + 1);
+    for (size_t k = 0; k < c.gates.size(); ++k) by_level[glev[k]].push_back((uint32_t)k);
+    std::vector<uint4> desc;
+    desc.reserve(c.gates.size() * count);
+    P->levels = depth;
+    P->gates = (uint64_t)c.gates.size() * count;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        P->level_off.push_back((uint32_t)desc.size());
+        for (size_t inst = 0; inst < count; ++inst)
+            for (uint32_t k : by_level[L]) {
+                const Gate& g = c.gates[k];
+                desc.push_back(make_uint4(g.op, gid(g.in0, inst), gid(g.in1, inst), gid(g.out, inst)));
+            }
+        const uint32_t wdt = (uint32_t)(desc.size() - P->level_off.back());
+        P->level_width.push_back(wdt);
+        P->max_width = std::max(P->max_width, wdt);
+    }
+    hipError_t e = hipMalloc((void**)&P->desc, std::max<size_t>(desc.size(), 1) * sizeof(uint4));
+    if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
+    e = hipMemcpy(P->desc, desc.data(), desc.size() * sizeof(uint4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
+    if (npool) {
+        e = hipMalloc((void**)&P->pool, (size_t)npool * count * kLweW * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(e, "circuit pool");
+    }
+    return ctx_reserve_big(ctx, P->max_width);
+}
+
+void free_plan(Plan& P) {
+    if (P.desc) (void)hipFree(P.desc);
+    if (P.pool) (void)hipFree(P.pool);
+    P.desc = nullptr;
+    P.pool = nullptr;
+}
+
+int get_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, size_t count, Plan** out) {
+    if (!ctx->circuits) ctx->circuits = new CircuitCache();
+    auto key = std::make_tuple(kind, w, rows, cols, count);
+    auto it = ctx->circuits->plans.find(key);
+    if (it != ctx->circuits->plans.end()) {
+        *out = &it->second;
+        return FHE_OK;
+    }
+    Plan P;
+    int rc = build_plan(ctx, kind, w, rows, cols, count, &P);
+    if (rc) {
+        free_plan(P);
+        return rc;
+    }
+    *out = &(ctx->circuits->plans[key] = P);
+    return FHE_OK;
+}
+
+int run_circuit(fhe_ctx* ctx, int kind, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                uint32_t w, uint32_t rows, uint32_t cols, hipStream_t s, const char* name) {
+    if (!ctx) return set_error(FHE_EINVAL, "%s: null context", name);
+    if (w < 1 || w > 64) return set_error(FHE_EINVAL, "%s: width %u not in 1..64", name, w);
+    if (count == 0) return FHE_OK;
+    if (!A || !B || !R) return set_error(FHE_EINVAL, "%s: null buffer", name);
+    DeviceGuard guard(ctx->device);
+    Plan* P = nullptr;
+    int rc = get_plan(ctx, kind, w, rows, cols, count, &P);
+    if (rc) return rc;
+    dev::GateIO io{};
+    io.region[kRegionA] = const_cast<uint32_t*>(A);
+    io.region[kRegionB] = const_cast<uint32_t*>(B);
+    io.region[kRegionR] = R;
+    io.region[kRegionPool] = P->pool;
+    for (uint32_t L = 0; L < P->levels; ++L) {
+        io.desc = P->desc + P->level_off[L];
+        rc = run_gate_batch(ctx, io, P->level_width[L], s);
+        if (rc) return rc;
+    }
+    return FHE_OK;
+}
+
+}  // namespace
+
+void destroy_circuit_cache(fhe_ctx* ctx) {
+    if (!ctx->circuits) return;
+    for (auto& kv : ctx->circuits->plans) free_plan(kv.second);
+    delete ctx->circuits;
+    ctx->circuits = nullptr;
+}
+
+}  // namespace fhe
+
+using namespace fhe;
+
+extern "C" int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                       uint32_t width, void* stream) {
+    return run_circuit(ctx, kAdd, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add");
+}
+
+extern "C" int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                       uint32_t width, void* stream) {
+    return run_circuit(ctx, kMul, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul");
+}
+
+extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
+                          uint32_t cols, uint32_t width, void* stream) {
+    if (rows == 0 || cols == 0) return set_error(FHE_EINVAL, "fhe_matvec: empty matrix");
+    return run_circuit(ctx, kMatvec, M, x, y, 1, width, rows, cols, (hipStream_t)stream, "fhe_matvec");
+}
+
+extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,
+                                 uint32_t* levels, uint64_t* widest_level) {
+    if (kind < 0 || kind > 2 || width < 1 || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
+        return set_error(FHE_EINVAL, "fhe_circuit_shape: bad arguments");
+    const Circuit c = build_circuit(kind, width, rows, cols);
+    uint32_t depth = 0;
+    const std::vector<uint32_t> glev = asap_levels(c, &depth);
+    std::vector<uint64_t> per(depth + 1, 0);
+    for (uint32_t l : glev) per[l]++;
+    if (gates) *gates = c.gates.size();
+    if (levels) *levels = depth;
+    if (widest_level) *widest_level = *std::max_element(per.begin(), per.end());
+    return FHE_OK;
+}

@@ -1,0 +1,55 @@
+// Launchers of the gfx950 kernels (kernels.hip), called by the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fhe {
+namespace dev {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlockThreads = 64 * kWavesPerBlock;
+
+// Where a batch of gates reads its operands and writes its results.
+//  Direct mode (desc == nullptr): gate g reads in0 + g*(n+1), in1 + g*(n+1),
+//  writes out + g*(n+1); its code is ops[g], or op_const when ops == nullptr.
+//  Descriptor mode: desc[g] = {op, in0 wire, in1 wire, out wire}; a wire id
+//  is (region << 30) | index and addresses region[region] + index*(n+1).
+struct GateIO {
+    const uint4* desc;
+    const uint8_t* ops;
+    uint32_t op_const;
+    const uint32_t* in0;
+    const uint32_t* in1;
+    uint32_t* out;
+    uint32_t* region[4];
+};
+
+// Per-context device key material.
+struct DeviceKeys {
+    const uint64_t* bkd;      // BK in the NTT domain, kernel layout (32 MB)
+    const uint32_t* ksk;      // KSK rows v = 1..3, [N][t][3][512] (50 MB)
+    const uint32_t* zero_row; // 512 zero words (digit 0 rows)
+    const uint64_t* twf;      // forward twiddles [32][32]
+    const uint64_t* twi;      // inverse twiddles (with N^-1) [32][32]
+};
+
+// BK (uint32 [n][2l][2][N], device) -> NTT-domain kernel layout.
+hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* twf,
+                             uint32_t n_lwe, hipStream_t s);
+
+// Gate prologue + blind rotation + sample extraction: writes big[g][N+1].
+hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
+                               uint32_t count, hipStream_t s);
+
+// Key switching big[g] -> the gate's output sample.
+hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
+                             uint32_t count, hipStream_t s);
+
+// One CMux on acc[2][N] (device) with prepared BK_i (bkd of one iteration).
+hipError_t launch_debug_cmux(const DeviceKeys& K, const uint64_t* bkd_i, int32_t abar,
+                             uint32_t* acc, hipStream_t s);
+
+}  // namespace dev
+}  // namespace fhe

@@ -1,0 +1,499 @@
+// gfx950 kernels of TFHE gate bootstrapping.
+//
+// Arithmetic: the negacyclic products of the CMux external product are done
+// as an exact NTT over Z_p, p = 2^64 - 2^32 + 1.  Digits are in [-512, 511]
+// and key words are read as signed 32-bit, so every coefficient of a summed
+// product is below 4 * 1024 * 2^9 * 2^31 = 2^52 < p/2 in magnitude and lifts
+// back to Z/2^32 exactly: results equal the schoolbook definition bit for bit.
+//
+// Work layout: one wavefront (64 lanes) bootstraps one gate.  Lane
+// l = 32h + t (half h, t < 32) keeps, for polynomial h of the accumulator,
+// coefficients m = t + 32*q in register q (q < 32).  A 1024-point negacyclic
+// NTT is split 32 x 32: a 32-point negacyclic transform in registers over q
+// (root psi^32 = 8, so every twiddle is a power of two: shifts only), one
+// general twiddle psi^(t(2j+1)) per value, a transpose through LDS, and a
+// 32-point cyclic transform in registers (root psi^64 = 2^6).  After it, lane
+// (h, t) register q holds frequency k = t + 32*brv5(q).  The inverse runs the
+// same steps backwards; N^-1 is folded into its twiddles.
+//
+// CMux i (TFHE blind rotation): D = X^abar_i ACC - ACC; each half extracts
+// its own gadget digit (half h -> digit h) of polynomial hp = 0, 1 in two
+// passes, transforms it, swaps it with the other half (v_permlane32_swap),
+// and half h accumulates output column h against BK_i in the NTT domain.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fhe_internal.h"
+#include "goldilocks.h"
+#include "kernels.h"
+
+namespace fhe {
+namespace dev {
+namespace {
+
+constexpr int N = 1024;
+constexpr int NW = 501;            // LWE sample words
+constexpr int NLWE = 500;
+constexpr uint32_t kDecompOffset = 0x80200800u;  // 2^31 + 2^21 + 2^11
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+__host__ __device__ constexpr int brv5(int x) {
+    return ((x & 1) << 4) | ((x & 2) << 2) | (x & 4) | ((x & 8) >> 2) | ((x & 16) >> 4);
+}
+
+// ---------------------------------------------------------------------------
+// 32-point transforms in registers.
+// ---------------------------------------------------------------------------
+
+// Negacyclic forward, root psi2 = 8 (order 64), natural in, bit-reversed out:
+// out[q] = sum_i x[i] psi2^(i (2 brv5(q) + 1)).  Merged Cooley-Tukey.
+__device__ __forceinline__ void ntt32_neg_fwd(uint64_t (&x)[32]) {
+    static_for<0, 5>([&](auto L) {
+        constexpr int m = 1 << decltype(L)::value;
+        constexpr int t = 16 >> decltype(L)::value;
+        static_for<0, m>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int S = 3 * brv5(m + i);
+            static_for<0, t>([&](auto J) {
+                constexpr int j = 2 * i * t + decltype(J)::value;
+                const uint64_t U = x[j];
+                const uint64_t V = gl::mul_pow2<S>(x[j + t]);
+                x[j] = gl::add(U, V);
+                x[j + t] = gl::sub(U, V);
+            });
+        });
+    });
+}
+
+// Cyclic forward, root w = 2^6 (order 32), natural in, bit-reversed out.
+// Decimation in frequency.
+__device__ __forceinline__ void ntt32_cyc_fwd(uint64_t (&x)[32]) {
+    static_for<0, 5>([&](auto L) {
+        constexpr int ln = 16 >> decltype(L)::value;
+        static_for<0, 16 / ln>([&](auto B) {
+            constexpr int st = 2 * ln * decltype(B)::value;
+            static_for<0, ln>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                constexpr int S = 6 * j * (16 / ln);
+                const uint64_t U = x[st + j], V = x[st + j + ln];
+                x[st + j] = gl::add(U, V);
+                x[st + j + ln] = gl::mul_pow2<S>(gl::sub(U, V));
+            });
+        });
+    });
+}
+
+// Inverse of ntt32_cyc_fwd without the 1/32: bit-reversed in, natural out.
+// w^-s = -2^(96-s).
+__device__ __forceinline__ void ntt32_cyc_inv(uint64_t (&x)[32]) {
+    static_for<0, 5>([&](auto L) {
+        constexpr int ln = 1 << decltype(L)::value;
+        static_for<0, 16 / ln>([&](auto B) {
+            constexpr int st = 2 * ln * decltype(B)::value;
+            static_for<0, ln>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                constexpr int S = 6 * j * (16 / ln);
+                const uint64_t U = x[st + j], V = x[st + j + ln];
+                if constexpr (S == 0) {
+                    x[st + j] = gl::add(U, V);
+                    x[st + j + ln] = gl::sub(U, V);
+                } else {
+                    const uint64_t W = gl::mul_pow2<96 - S>(V);
+                    x[st + j] = gl::sub(U, W);
+                    x[st + j + ln] = gl::add(U, W);
+                }
+            });
+        });
+    });
+}
+
+// Inverse of ntt32_neg_fwd without the 1/32: bit-reversed in, natural out.
+// Gentleman-Sande; psi2^-e = -2^(96-e), so (U - V) psi2^-e = (V - U) 2^(96-e).
+__device__ __forceinline__ void ntt32_neg_inv(uint64_t (&x)[32]) {
+    static_for<0, 5>([&](auto L) {
+        constexpr int t = 1 << decltype(L)::value;
+        constexpr int h = 16 >> decltype(L)::value;
+        static_for<0, h>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int E = 3 * brv5(h + i);
+            static_for<0, t>([&](auto J) {
+                constexpr int j = 2 * t * i + decltype(J)::value;
+                const uint64_t U = x[j], V = x[j + t];
+                x[j] = gl::add(U, V);
+                x[j + t] = gl::mul_pow2<96 - E>(gl::sub(V, U));
+            });
+        });
+    });
+}
+
+// Orders the wave's LDS traffic: LDS operations of one wavefront execute in
+// issue order, so a compiler-level barrier is all a wave-private exchange
+// needs.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Full 1024-point forward negacyclic NTT of this half's polynomial.
+// xb: this half's 32 x 32 LDS tile; element (row, col) at row*32 + (col ^ row).
+__device__ __forceinline__ void ntt1024_fwd(uint64_t (&x)[32], uint64_t* xb,
+                                            const uint64_t* twf, int t) {
+    ntt32_neg_fwd(x);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) x[q] = gl::mul(x[q], twf[q * 32 + t]);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int row = brv5(q);
+        xb[row * 32 + (t ^ row)] = x[q];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 32; ++r) x[r] = xb[t * 32 + (r ^ t)];
+    wave_lds_sync();
+    ntt32_cyc_fwd(x);
+}
+
+// Inverse of ntt1024_fwd including N^-1 (folded in twi).
+__device__ __forceinline__ void ntt1024_inv(uint64_t (&x)[32], uint64_t* xb,
+                                            const uint64_t* twi, int t) {
+    ntt32_cyc_inv(x);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) x[r] = gl::mul(x[r], twi[r * 32 + t]);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) xb[r * 32 + (t ^ r)] = x[r];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int col = brv5(q);
+        x[q] = xb[t * 32 + (col ^ t)];
+    }
+    wave_lds_sync();
+    ntt32_neg_inv(x);
+}
+
+// Value of the other half's lane with the same t.
+__device__ __forceinline__ uint32_t partner32(uint32_t v, int h) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return h ? r[0] : r[1];
+}
+
+__device__ __forceinline__ uint64_t partner64(uint64_t v, int h) {
+    const uint32_t lo = partner32((uint32_t)v, h);
+    const uint32_t hi = partner32((uint32_t)(v >> 32), h);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Shared-memory footprint of one block: twiddles plus one 16 KB tile pair
+// per wave.
+struct BlockLds {
+    uint64_t twf[32 * 32];
+    uint64_t twi[32 * 32];
+    uint64_t tile[kWavesPerBlock][2][32 * 32];
+};
+
+// One CMux step on this wave's accumulator (acc: lane (h, t) register q =
+// coefficient t + 32q of polynomial h).  bk_i: BK_i in the kernel layout
+// [hp][q][sel][64 lanes].
+__device__ __forceinline__ void cmux_step(uint32_t (&acc)[32], int ai, const uint64_t* __restrict__ bk_i,
+                                          uint64_t* tile /* 2 x 1024 u64 */, const uint64_t* twf,
+                                          const uint64_t* twi, int lane) {
+    const int h = lane >> 5, t = lane & 31;
+    uint64_t* xb = tile + h * 1024;
+    uint32_t* accs = reinterpret_cast<uint32_t*>(tile);  // 1024 words, reused
+    const int shift = 22 - 10 * h;                        // digit h of the gadget
+    uint64_t mac[32];
+    uint64_t x[32];
+
+#pragma unroll
+    for (int hp = 0; hp < 2; ++hp) {
+        // Publish polynomial hp of the accumulator, then form
+        // D = X^ai ACC_hp - ACC_hp and this half's digit of every coefficient.
+        if (h == hp) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) accs[t + 32 * q] = acc[q];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int m = t + 32 * q;
+            const int s = (m - ai) & 2047;
+            const uint32_t v = accs[s & 1023];
+            const uint32_t rot = (s & 1024) ? 0u - v : v;
+            const uint32_t D = rot - accs[m];
+            const int32_t dg = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
+            x[q] = gl::from_i64(dg);
+        }
+        wave_lds_sync();
+        ntt1024_fwd(x, xb, twf, t);
+        // Multiply-accumulate against BK_i rows (2hp + h) and (2hp + 1 - h),
+        // column h, in the NTT domain.
+        const uint64_t* bkp = bk_i + (size_t)hp * (32 * 2 * 64) + lane;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const uint64_t other = partner64(x[q], h);
+            const uint64_t b_own = bkp[(q * 2 + 0) * 64];
+            const uint64_t b_oth = bkp[(q * 2 + 1) * 64];
+            const uint64_t v = gl::add(gl::mul(x[q], b_own), gl::mul(other, b_oth));
+            mac[q] = hp == 0 ? v : gl::add(mac[q], v);
+        }
+    }
+    ntt1024_inv(mac, xb, twi, t);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] += gl::lift32(gl::canon(mac[q]));
+}
+
+// Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding).
+__device__ __forceinline__ void gate_consts(uint32_t op, uint32_t& kappa, int32_t& s1, int32_t& s2) {
+    constexpr uint32_t mu = kMu;
+    switch (op) {
+    case FHE_AND:   kappa = 0u - mu;      s1 = 1;  s2 = 1;  break;
+    case FHE_NAND:  kappa = mu;           s1 = -1; s2 = -1; break;
+    case FHE_OR:    kappa = mu;           s1 = 1;  s2 = 1;  break;
+    case FHE_NOR:   kappa = 0u - mu;      s1 = -1; s2 = -1; break;
+    case FHE_XOR:   kappa = 2u * mu;      s1 = 2;  s2 = 2;  break;
+    case FHE_XNOR:  kappa = 0u - 2u * mu; s1 = -2; s2 = -2; break;
+    case FHE_ANDNY: kappa = 0u - mu;      s1 = -1; s2 = 1;  break;
+    case FHE_ANDYN: kappa = 0u - mu;      s1 = 1;  s2 = -1; break;
+    case FHE_ORNY:  kappa = mu;           s1 = -1; s2 = 1;  break;
+    default:        kappa = mu;           s1 = 1;  s2 = -1; break;  // FHE_ORYN
+    }
+}
+
+__device__ __forceinline__ uint32_t* wire_ptr(const GateIO& io, uint32_t w) {
+    return io.region[w >> 30] + (size_t)(w & 0x3FFFFFFFu) * NW;
+}
+
+__device__ __forceinline__ void gate_operands(const GateIO& io, uint32_t g, uint32_t& op,
+                                              const uint32_t*& c1, const uint32_t*& c2) {
+    if (io.desc) {
+        const uint4 d = io.desc[g];
+        op = d.x;
+        c1 = wire_ptr(io, d.y);
+        c2 = wire_ptr(io, d.z);
+    } else {
+        op = io.ops ? io.ops[g] : io.op_const;
+        c1 = io.in0 + (size_t)g * NW;
+        c2 = io.in1 + (size_t)g * NW;
+    }
+}
+
+__device__ __forceinline__ uint32_t* gate_output(const GateIO& io, uint32_t g) {
+    return io.desc ? wire_ptr(io, io.desc[g].w) : io.out + (size_t)g * NW;
+}
+
+__device__ __forceinline__ void load_twiddles(BlockLds& S, const uint64_t* twf, const uint64_t* twi) {
+    for (int k = threadIdx.x; k < 1024; k += kBlockThreads) {
+        S.twf[k] = twf[k];
+        S.twi[k] = twi[k];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+// Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
+// sample extraction.  One wave per gate, four gates per block.
+__global__ __launch_bounds__(kBlockThreads) void k_blind_rotate(DeviceKeys K, GateIO io,
+                                                                uint32_t* __restrict__ big,
+                                                                uint32_t count) {
+    __shared__ BlockLds S;
+    load_twiddles(S, K.twf, K.twi);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * kWavesPerBlock + wave;
+    if (g >= count) return;
+    const int h = lane >> 5, t = lane & 31;
+
+    // Prologue: combined sample, modulus switched to Z_2N.  Lane l keeps
+    // abar of words l + 64k in ab[k].
+    uint32_t op;
+    const uint32_t *c1, *c2;
+    gate_operands(io, g, op, c1, c2);
+    uint32_t kappa;
+    int32_t s1, s2;
+    gate_consts(op, kappa, s1, s2);
+    uint32_t ab[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int w = lane + 64 * k;
+        uint32_t v = 0;
+        if (w < NW) {
+            v = (uint32_t)s1 * c1[w] + (uint32_t)s2 * c2[w];
+            if (w == NLWE) v += kappa;
+        }
+        ab[k] = (v + (1u << 20)) >> 21;
+    }
+    const int bbar = __builtin_amdgcn_readlane(ab[7], NLWE - 448);
+
+    // ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... + X^(N-1)).
+    uint32_t acc[32];
+    {
+        const int c = (2 * N - bbar) & (2 * N - 1);
+        const int cm = c & (N - 1);
+        const uint32_t neg = (c >= N) ? 1u : 0u;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int m = t + 32 * q;
+            const uint32_t sgn = (m >= cm) ? neg : 1u - neg;  // 1 -> -mu
+            acc[q] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
+        }
+    }
+
+    uint64_t* tile = &S.tile[wave][0][0];
+    const uint64_t* bk = K.bkd;
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        const int lim = (NLWE - 64 * k) < 64 ? (NLWE - 64 * k) : 64;
+#pragma unroll 1
+        for (int l = 0; l < lim; ++l) {
+            const int ai = __builtin_amdgcn_readlane(ab[0], l);
+            if (ai != 0) cmux_step(acc, ai, bk, tile, S.twf, S.twi, lane);
+            bk += 2 * 32 * 2 * 64;
+        }
+#pragma unroll
+        for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+    }
+
+    // Sample extraction of coefficient 0: a'_0 = a_0, a'_m = -a_(N-m), b' = b_0.
+    uint32_t* o = big + (size_t)g * (N + 1);
+    if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int m = t + 32 * q;
+            if (m == 0) o[0] = acc[q];
+            else o[N - m] = 0u - acc[q];
+        }
+    } else if (t == 0) {
+        o[N] = acc[0];
+    }
+}
+
+// Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
+// j-th base-4 digit of a'_i rounded to 16 bits.  One wave per gate; lane l
+// owns output words 8l .. 8l+7 and gathers 2 KB rows with 16-byte loads.
+__global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, GateIO io,
+                                                              const uint32_t* __restrict__ big,
+                                                              uint32_t count) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * kWavesPerBlock + wave;
+    if (g >= count) return;
+    const uint32_t* src = big + (size_t)g * (N + 1);
+    uint32_t acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = (8 * lane + e == NLWE) ? src[N] : 0u;
+    const uint4* zero = reinterpret_cast<const uint4*>(K.zero_row);
+#pragma unroll 1
+    for (int i0 = 0; i0 < N; i0 += 64) {
+        const uint32_t digits = (src[i0 + lane] + (1u << 15)) >> 16;
+#pragma unroll 1
+        for (int l = 0; l < 64; ++l) {
+            const uint32_t dd = __builtin_amdgcn_readlane(digits, l);
+            const size_t rowbase = ((size_t)(i0 + l) * kKsT) * 3;
+#pragma unroll
+            for (int j = 0; j < (int)kKsT; ++j) {
+                const uint32_t d = (dd >> (14 - 2 * j)) & 3u;
+                const uint4* row = d ? reinterpret_cast<const uint4*>(K.ksk + (rowbase + 3 * j + d - 1) * kKskRowWords)
+                                     : zero;
+                const uint4 v0 = row[2 * lane], v1 = row[2 * lane + 1];
+                acc[0] -= v0.x; acc[1] -= v0.y; acc[2] -= v0.z; acc[3] -= v0.w;
+                acc[4] -= v1.x; acc[5] -= v1.y; acc[6] -= v1.z; acc[7] -= v1.w;
+            }
+        }
+    }
+    uint32_t* o = gate_output(io, g);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
+}
+
+// BK (uint32 [n][4][2][N]) -> NTT domain in the layout cmux_step reads:
+// bkd[i][hp][q][sel][lane], lane = 32c + t, for row r = 2hp + digit, column c:
+// sel = 0 when digit == c (the half's own digit), 1 otherwise.
+__global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __restrict__ bk,
+                                                              uint64_t* __restrict__ bkd,
+                                                              const uint64_t* __restrict__ twf,
+                                                              uint32_t npolys) {
+    __shared__ uint64_t stw[32 * 32];
+    __shared__ uint64_t tiles[kWavesPerBlock][2][32 * 32];
+    for (int k = threadIdx.x; k < 1024; k += kBlockThreads) stw[k] = twf[k];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int h = lane >> 5, t = lane & 31;
+    const uint32_t base = 2 * (blockIdx.x * kWavesPerBlock + wave);
+    if (base >= npolys) return;
+    const uint32_t poly = base + h;  // npolys is even
+    uint64_t x[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) x[q] = gl::from_i64((int32_t)bk[(size_t)poly * N + t + 32 * q]);
+    ntt1024_fwd(x, &tiles[wave][h][0], stw, t);
+    const uint32_t i = poly / 8, r = (poly / 2) % 4, c = poly % 2;
+    const uint32_t hp = r >> 1, digit = r & 1, sel = (digit == c) ? 0 : 1;
+    uint64_t* dst = bkd + (size_t)i * (2 * 32 * 2 * 64) + (size_t)hp * (32 * 2 * 64) + 32 * c + t;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) dst[(q * 2 + sel) * 64] = gl::canon(x[q]);
+}
+
+// One CMux on acc[2][N] in global memory (single wave).
+__global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bkd_i,
+                                                   int32_t abar, uint32_t* __restrict__ accg) {
+    __shared__ uint64_t stw[2][32 * 32];
+    __shared__ uint64_t tile[2][32 * 32];
+    for (int k = threadIdx.x; k < 1024; k += 64) {
+        stw[0][k] = K.twf[k];
+        stw[1][k] = K.twi[k];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x, h = lane >> 5, t = lane & 31;
+    uint32_t acc[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = accg[h * N + t + 32 * q];
+    cmux_step(acc, abar, bkd_i, &tile[0][0], stw[0], stw[1], lane);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) accg[h * N + t + 32 * q] = acc[q];
+}
+
+}  // namespace
+
+hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* twf,
+                             uint32_t n_lwe, hipStream_t s) {
+    const uint32_t npolys = n_lwe * 8;
+    const uint32_t waves = npolys / 2;
+    const uint32_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_bk_prepare, dim3(blocks), dim3(kBlockThreads), 0, s, bk, bkd, twf, npolys);
+    return hipGetLastError();
+}
+
+hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
+                               uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_blind_rotate, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
+                             uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_key_switch, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_cmux(const DeviceKeys& K, const uint64_t* bkd_i, int32_t abar,
+                             uint32_t* acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_debug_cmux, dim3(1), dim3(64), 0, s, K, bkd_i, abar, acc);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace fhe

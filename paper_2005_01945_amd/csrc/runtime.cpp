@@ -1,0 +1,258 @@
+// Device context and gate-bootstrapping entry points.
+//
+// A context keeps the cloud key resident on one GPU: the bootstrapping key
+// converted once to the NTT domain (32.8 MB), the key-switching key laid out
+// as 2 KB rows (50.3 MB), and the twiddle tables.  Gate batches run as two
+// launches on the caller's stream: blind rotation (with the gate prologue and
+// sample extraction fused in) and key switching.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "fhe_internal.h"
+#include "goldilocks.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace fhe {
+
+namespace {
+
+constexpr int brv5h(int x) {
+    return ((x & 1) << 4) | ((x & 2) << 2) | (x & 4) | ((x & 8) >> 2) | ((x & 16) >> 4);
+}
+
+}  // namespace
+
+// The 2048-th root of unity psi with psi^32 = 8: then psi^32 and psi^64 are
+// powers of two and the in-register transforms need shifts only.
+uint64_t ntt_psi() {
+    const uint64_t psi0 = gl::pow(7, (gl::P - 1) / 2048);  // 7 generates Z_p^*
+    for (uint64_t u = 1; u < 2048; u += 2) {
+        const uint64_t c = gl::pow(psi0, u);
+        if (gl::pow(c, 32) == 8) return c;
+    }
+    return 0;
+}
+
+void make_twiddles(std::vector<uint64_t>& twf, std::vector<uint64_t>& twi) {
+    const uint64_t psi = ntt_psi();
+    const uint64_t ninv = gl::pow(kN, gl::P - 2);
+    twf.assign(1024, 0);
+    twi.assign(1024, 0);
+    for (int q = 0; q < 32; ++q)
+        for (int t = 0; t < 32; ++t)
+            twf[q * 32 + t] = gl::pow(psi, (uint64_t)(t * (2 * brv5h(q) + 1)) % 2048);
+    for (int r = 0; r < 32; ++r)
+        for (int t = 0; t < 32; ++t) {
+            const uint64_t e = (2048 - (uint64_t)(r * (2 * t + 1)) % 2048) % 2048;
+            twi[r * 32 + t] = gl::canon(gl::mul(ninv, gl::pow(psi, e)));
+        }
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    ok_ = hipSetDevice(dev) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return set_error(FHE_ENOMEM, "%s: out of device memory", what);
+    return set_error(FHE_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_gfx950(int device) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return set_error(FHE_EDEVICE, "no HIP device %d", device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return set_error(FHE_EDEVICE, "cannot query HIP device %d", device);
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(FHE_EDEVICE, "device %d is %s; this library is built for gfx950", device,
+                         prop.gcnArchName);
+    return FHE_OK;
+}
+
+int ctx_reserve_big(fhe_ctx* ctx, size_t gates) {
+    const size_t need = gates * (kN + 1);
+    if (need <= ctx->big_cap) return FHE_OK;
+    if (ctx->big) {
+        hipError_t e = hipDeviceSynchronize();  // work in flight may still read the old buffer
+        if (e != hipSuccess) return hip_fail(e, "scratch resize");
+        (void)hipFree(ctx->big);
+        ctx->big = nullptr;
+        ctx->big_cap = 0;
+    }
+    size_t cap = need < (size_t)4096 * (kN + 1) ? (size_t)4096 * (kN + 1) : need;
+    hipError_t e = hipMalloc((void**)&ctx->big, cap * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "scratch allocation");
+    ctx->big_cap = cap;
+    return FHE_OK;
+}
+
+int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s) {
+    if (count == 0) return FHE_OK;
+    int rc = ctx_reserve_big(ctx, count);
+    if (rc) return rc;
+    hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count, s);
+    if (e != hipSuccess) return hip_fail(e, "blind rotation launch");
+    e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)count, s);
+    if (e != hipSuccess) return hip_fail(e, "key switch launch");
+    return FHE_OK;
+}
+
+}  // namespace fhe
+
+using namespace fhe;
+
+extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out) {
+    if (!ck || !out) return set_error(FHE_EINVAL, "fhe_ctx_create: null argument");
+    *out = nullptr;
+    std::string why;
+    if (!params_supported(ck->P, &why)) return set_error(FHE_EINVAL, "fhe_ctx_create: %s", why.c_str());
+    int rc = check_gfx950(device);
+    if (rc) return rc;
+    DeviceGuard guard(device);
+    if (!guard.ok()) return set_error(FHE_EDEVICE, "cannot select device %d", device);
+
+    fhe_ctx* ctx = new (std::nothrow) fhe_ctx();
+    if (!ctx) return set_error(FHE_ENOMEM, "fhe_ctx_create: out of host memory");
+    ctx->device = device;
+    ctx->P = ck->P;
+
+    std::vector<uint64_t> twf, twi;
+    make_twiddles(twf, twi);
+    const size_t n = ck->P.n, N = ck->P.N;
+    const size_t bk_words = n * 4 * 2 * N;
+    const size_t bkd_words = n * 2 * 32 * 2 * 64;
+    const size_t ksk_rows = N * kKsT * 3;
+
+    // KS rows v = 1..3, each padded to 512 words.
+    std::vector<uint32_t> ksk_dev(ksk_rows * kKskRowWords, 0u);
+    for (size_t i = 0; i < N; ++i)
+        for (size_t j = 0; j < kKsT; ++j)
+            for (size_t v = 1; v < kKsBase; ++v)
+                std::memcpy(&ksk_dev[((i * kKsT + j) * 3 + v - 1) * kKskRowWords],
+                            &ck->ksk[((i * kKsT + j) * kKsBase + v) * (n + 1)], (n + 1) * sizeof(uint32_t));
+
+    uint32_t* bk_tmp = nullptr;
+    auto fail = [&](hipError_t e, const char* what) {
+        int code = hip_fail(e, what);
+        if (bk_tmp) (void)hipFree(bk_tmp);
+        fhe_ctx_destroy(ctx);
+        return code;
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) return fail(e, "stream");
+    if ((e = hipMalloc((void**)&ctx->twf, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
+    if ((e = hipMalloc((void**)&ctx->twi, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
+    if ((e = hipMalloc((void**)&ctx->bkd, bkd_words * 8)) != hipSuccess) return fail(e, "bootstrapping key");
+    if ((e = hipMalloc((void**)&ctx->ksk, ksk_dev.size() * 4)) != hipSuccess) return fail(e, "key-switching key");
+    if ((e = hipMalloc((void**)&ctx->zero_row, kKskRowWords * 4)) != hipSuccess) return fail(e, "zero row");
+    if ((e = hipMalloc((void**)&bk_tmp, bk_words * 4)) != hipSuccess) return fail(e, "bootstrapping key staging");
+    if ((e = hipMemcpy(ctx->twf, twf.data(), 1024 * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
+    if ((e = hipMemcpy(ctx->twi, twi.data(), 1024 * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
+    if ((e = hipMemcpy(ctx->ksk, ksk_dev.data(), ksk_dev.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "upload");
+    if ((e = hipMemset(ctx->zero_row, 0, kKskRowWords * 4)) != hipSuccess) return fail(e, "upload");
+    if ((e = hipMemcpy(bk_tmp, ck->bk.data(), bk_words * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "upload");
+    if ((e = dev::launch_bk_prepare(bk_tmp, ctx->bkd, ctx->twf, (uint32_t)n, ctx->stream)) != hipSuccess)
+        return fail(e, "bootstrapping key transform");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return fail(e, "bootstrapping key transform");
+    (void)hipFree(bk_tmp);
+    bk_tmp = nullptr;
+
+    ctx->keys.bkd = ctx->bkd;
+    ctx->keys.ksk = ctx->ksk;
+    ctx->keys.zero_row = ctx->zero_row;
+    ctx->keys.twf = ctx->twf;
+    ctx->keys.twi = ctx->twi;
+    *out = ctx;
+    return FHE_OK;
+}
+
+extern "C" void fhe_ctx_destroy(fhe_ctx* ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard guard(ctx->device);
+        (void)hipDeviceSynchronize();
+        destroy_circuit_cache(ctx);
+        for (void* p : {(void*)ctx->bkd, (void*)ctx->ksk, (void*)ctx->zero_row, (void*)ctx->twf,
+                        (void*)ctx->twi, (void*)ctx->big})
+            if (p) (void)hipFree(p);
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+extern "C" int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0,
+                                        const uint32_t* in1, uint32_t* out, size_t count, void* stream) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_batch: null context");
+    if (count == 0) return FHE_OK;
+    if (!ops || !in0 || !in1 || !out) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_batch: null buffer");
+    if (count > (size_t)1 << 30) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_batch: count %zu too large", count);
+    DeviceGuard guard(ctx->device);
+    dev::GateIO io{};
+    io.ops = ops;
+    io.in0 = in0;
+    io.in1 = in1;
+    io.out = out;
+    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+}
+
+extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
+                                        const uint32_t* in1, uint32_t* out, void* stream) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_plain: null context");
+    if (!in0 || !in1 || !out) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_plain: null buffer");
+    if (op > FHE_ORYN) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_plain: gate code %u", op);
+    DeviceGuard guard(ctx->device);
+    dev::GateIO io{};
+    io.op_const = op;
+    io.in0 = in0;
+    io.in1 = in1;
+    io.out = out;
+    int rc = run_gate_batch(ctx, io, 1, (hipStream_t)stream);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_bootstrap_gate_plain");
+}
+
+extern "C" int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, uint32_t* acc) {
+    if (!bk_i || !acc || abar < 0 || abar >= 2 * (int)kN)
+        return set_error(FHE_EINVAL, "fhe_debug_cmux: bad argument");
+    int rc = check_gfx950(device);
+    if (rc) return rc;
+    DeviceGuard guard(device);
+    std::vector<uint64_t> twf, twi;
+    make_twiddles(twf, twi);
+    uint64_t *d_twf = nullptr, *d_twi = nullptr, *d_bkd = nullptr;
+    uint32_t *d_bk = nullptr, *d_acc = nullptr;
+    const size_t bk_words = 4 * 2 * kN, bkd_words = 2 * 32 * 2 * 64;
+    hipError_t e = hipSuccess;
+    auto step = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    step(hipMalloc((void**)&d_twf, 8192));
+    step(hipMalloc((void**)&d_twi, 8192));
+    step(hipMalloc((void**)&d_bkd, bkd_words * 8));
+    step(hipMalloc((void**)&d_bk, bk_words * 4));
+    step(hipMalloc((void**)&d_acc, 2 * kN * 4));
+    if (e == hipSuccess) {
+        step(hipMemcpy(d_twf, twf.data(), 8192, hipMemcpyHostToDevice));
+        step(hipMemcpy(d_twi, twi.data(), 8192, hipMemcpyHostToDevice));
+        step(hipMemcpy(d_bk, bk_i, bk_words * 4, hipMemcpyHostToDevice));
+        step(hipMemcpy(d_acc, acc, 2 * kN * 4, hipMemcpyHostToDevice));
+    }
+    if (e == hipSuccess) step(dev::launch_bk_prepare(d_bk, d_bkd, d_twf, 1, nullptr));
+    dev::DeviceKeys K{};
+    K.twf = d_twf;
+    K.twi = d_twi;
+    if (e == hipSuccess) step(dev::launch_debug_cmux(K, d_bkd, abar, d_acc, nullptr));
+    if (e == hipSuccess) step(hipDeviceSynchronize());
+    if (e == hipSuccess) step(hipMemcpy(acc, d_acc, 2 * kN * 4, hipMemcpyDeviceToHost));
+    for (void* p : {(void*)d_twf, (void*)d_twi, (void*)d_bkd, (void*)d_bk, (void*)d_acc})
+        if (p) (void)hipFree(p);
+    return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_debug_cmux");
+}

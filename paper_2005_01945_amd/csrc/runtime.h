@@ -1,0 +1,54 @@
+// Context state and helpers shared by the runtime, circuit and serving sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <vector>
+
+#include "fhe_internal.h"
+#include "kernels.h"
+
+namespace fhe {
+struct CircuitCache;
+}
+
+struct fhe_ctx {
+    int device = 0;
+    fhe_params P{};
+    hipStream_t stream = nullptr;  // internal stream (key preparation)
+    uint64_t* bkd = nullptr;
+    uint32_t* ksk = nullptr;
+    uint32_t* zero_row = nullptr;
+    uint64_t* twf = nullptr;
+    uint64_t* twi = nullptr;
+    uint32_t* big = nullptr;  // extracted samples of the gates in flight, [gates][N+1]
+    size_t big_cap = 0;       // words
+    fhe::dev::DeviceKeys keys{};
+    fhe::CircuitCache* circuits = nullptr;
+};
+
+namespace fhe {
+
+// Makes `dev` current for the lifetime of the guard, restoring the caller's.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = -1;
+    bool ok_ = false;
+};
+
+int hip_fail(hipError_t e, const char* what);
+int check_gfx950(int device);
+uint64_t ntt_psi();
+void make_twiddles(std::vector<uint64_t>& twf, std::vector<uint64_t>& twi);
+int ctx_reserve_big(fhe_ctx* ctx, size_t gates);
+// Enqueues blind rotation + key switching of `count` gates on stream s.
+int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s);
+void destroy_circuit_cache(fhe_ctx* ctx);
+
+}  // namespace fhe
