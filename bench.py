@@ -1,0 +1,247 @@
+"""Benchmark: bootstrapped gates/s on one MI355X, batched vs plain, plus the
+latency of one 32-bit multiplication.
+
+One step = one batched 16-bit ripple-carry addition of 1024 encrypted pairs
+(75,776 bootstrapped gates in 30 levels, each level one launch pair), with
+inputs resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config add16|mul32|matvec]
+                  [--plain-reps R] [--mul-samples S] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one gate bootstrap (radix-2 NTT cost model of the method:
+# 500 CMux x (6 NTT-1024 of 5,120 butterflies + 8 x 1,024 pointwise MACs)),
+# in 32-bit integer lane operations: 26 per Goldilocks modmul (four 32x32->64
+# multiplies at quarter rate + reduction), 4 per modular add/sub.
+MODMUL_PER_GATE = 500 * (6 * 5120 + 8 * 1024)
+MODADD_PER_GATE = 500 * (6 * 5120 * 2 + 8 * 1024)
+LANE_OPS_PER_GATE = 26 * MODMUL_PER_GATE + 4 * MODADD_PER_GATE
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blind_rotate_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2005_01945_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(gates_per_launch):
+    """HBM bytes per blind-rotation launch from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t["bytes_per_gate"] * gates_per_launch
+
+
+def host_threads():
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(sk, a, b, width, sample_gates):
+    """The oracle on the host cores, on the first level of the same addition
+    workload (independent XOR/AND gates of fresh inputs)."""
+    import oracle
+    K = oracle.Keys(0)
+    ca = sk.encrypt_uint(a[: sample_gates], width, nonce=0)
+    cb = sk.encrypt_uint(b[: sample_gates], width, nonce=1 << 40)
+    ops, i0, i1 = [], [], []
+    for c in range(sample_gates):
+        for bit in range(width):
+            for op in (4, 0):  # XOR, AND of (a_i, b_i)
+                if len(ops) < sample_gates:
+                    ops.append(op)
+                    i0.append(ca[c, bit])
+                    i1.append(cb[c, bit])
+    threads = host_threads()
+    t0 = time.perf_counter()
+    K.bootstrap(ops, np.array(i0), np.array(i1), threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(ops) / dt, 3), "unit": "gates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ops)} gates of level 1 of the add16 workload (XOR/AND of fresh inputs), "
+                      f"{dt:.1f} s on {threads} threads; per-gate work is identical on every level"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="add16", choices=["add16", "mul32", "matvec"])
+    ap.add_argument("--plain-reps", type=int, default=5)
+    ap.add_argument("--mul-samples", type=int, default=5)
+    ap.add_argument("--cpu-sample-gates", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path shards by independent gates, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_01945_amd as F
+    import workloads
+
+    sk, ck = F.fhe_keygen(0)
+    ctx = F.Context(ck, 0)
+    stream = torch.cuda.current_stream()
+
+    if args.config == "add16":
+        wl = workloads.AddWorkload()
+        a, b = wl.operands()
+        width, count = wl.width, wl.count
+        ca, cb = sk.encrypt_uint(a, width, nonce=0), sk.encrypt_uint(b, width, nonce=1 << 40)
+        dA, dB = F.to_device(ca), F.to_device(cb)
+        dR = torch.empty_like(dA)
+        step = lambda: F.fhe_add(ctx, dA, dB, dR, count, width, stream)
+        gates, levels, _ = F.fhe_circuit_shape("add", width)
+        expect = (a + b) % (1 << width)
+        workload = {"workload": f"batched {width}-bit ripple-carry addition", "pairs": count,
+                    "width": width, "gates_per_step": gates * count, "levels": levels}
+    elif args.config == "mul32":
+        wl = workloads.MulWorkload()
+        a, b = wl.operands()
+        width, count = wl.width, wl.count
+        ca, cb = sk.encrypt_uint(a, width, nonce=0), sk.encrypt_uint(b, width, nonce=1 << 40)
+        dA, dB = F.to_device(ca), F.to_device(cb)
+        dR = torch.empty_like(dA)
+        step = lambda: F.fhe_mul(ctx, dA, dB, dR, count, width, stream)
+        gates, levels, _ = F.fhe_circuit_shape("mul", width)
+        expect = (a * b) % (1 << width)
+        workload = {"workload": f"batched {width}-bit shift-and-add multiplication", "pairs": count,
+                    "width": width, "gates_per_step": gates * count, "levels": levels}
+    else:
+        wl = workloads.MatvecWorkload()
+        M, x = wl.operands()
+        width = wl.width
+        cm = sk.encrypt_uint(M.reshape(-1), width, nonce=0)
+        cx = sk.encrypt_uint(x, width, nonce=1 << 40)
+        dA, dB = F.to_device(cm), F.to_device(cx)
+        dR = torch.empty((wl.rows, width, F.WORDS), dtype=torch.int32, device="cuda")
+        step = lambda: F.fhe_matvec(ctx, dA, dB, dR, wl.rows, wl.cols, width, stream)
+        gates, levels, _ = F.fhe_circuit_shape("matvec", width, wl.rows, wl.cols)
+        count = 1
+        expect = (M @ x) % (1 << width)
+        workload = {"workload": f"encrypted {wl.rows}x{wl.cols} matrix-vector product, {width}-bit",
+                    "rows": wl.rows, "cols": wl.cols, "width": width, "gates_per_step": gates, "levels": levels}
+    gates_per_step = gates * count
+
+    log(f"config {args.config}: {gates_per_step} gates/step, {levels} levels; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.fhe_ctx_timing(ctx)  # drop anything recorded so far
+    F.fhe_ctx_set_timing(ctx, True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    F.fhe_ctx_set_timing(ctx, False)
+    br_ms, ks_ms, launches, timed_gates = F.fhe_ctx_timing(ctx)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = gates_per_step / (ms_per_step / 1e3)
+    log(f"{ms_per_step:.1f} ms/step, {value:.0f} gates/s; blind rotation {br_ms:.1f} ms, "
+        f"key switch {ks_ms:.1f} ms over {launches} launches")
+
+    got = sk.decrypt_uint(F.to_host(dR), width)
+    if not np.array_equal(got, np.asarray(expect).reshape(-1).astype(np.uint64)):
+        raise SystemExit("bench: decrypted results differ from plaintext arithmetic")
+
+    # roofline of the dominant kernel (blind rotation), from the timed region
+    gates_per_launch = timed_gates / max(launches, 1)
+    avg_launch_ms = br_ms / max(launches, 1)
+    achieved = LANE_OPS_PER_GATE * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(gates_per_launch),
+                "kernel": "k_blind_rotate", "avg_launch_ms": round(avg_launch_ms, 3),
+                "gates_per_launch": round(gates_per_launch, 1)}
+
+    # plain path: one gate per launch, synchronous
+    a_bits, b_bits = workloads.truth_table_inputs()
+    p0 = F.to_device(sk.encrypt_bits(a_bits, nonce=1 << 50))
+    p1 = F.to_device(sk.encrypt_bits(b_bits, nonce=(1 << 50) + 100))
+    pout = torch.empty_like(p0)
+    for g in range(4):
+        F.fhe_bootstrap_gate_plain(ctx, F.NAND, p0[g], p1[g], pout[g], stream)
+    lat = []
+    for _ in range(args.plain_reps):
+        for g in range(4):
+            s0 = time.perf_counter()
+            F.fhe_bootstrap_gate_plain(ctx, F.NAND, p0[g], p1[g], pout[g], stream)
+            lat.append(time.perf_counter() - s0)
+    plain = {"gates_per_s": round(len(lat) / sum(lat), 2), "p50_ms": round(1e3 * float(np.median(lat)), 3),
+             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)}
+    log(f"plain: {plain}")
+
+    # latency of one 32-bit multiplication (one pair, 120 levels)
+    mul = None
+    if args.mul_samples > 0:
+        ma = workloads.uniform_uints(11, 1, 32)
+        mb = workloads.uniform_uints(12, 1, 32)
+        mA = F.to_device(sk.encrypt_uint(ma, 32, nonce=1 << 52))
+        mB = F.to_device(sk.encrypt_uint(mb, 32, nonce=(1 << 52) + 64))
+        mR = torch.empty_like(mA)
+        F.fhe_mul(ctx, mA, mB, mR, 1, 32, stream)
+        torch.cuda.synchronize()
+        ml = []
+        for _ in range(args.mul_samples):
+            s0 = time.perf_counter()
+            F.fhe_mul(ctx, mA, mB, mR, 1, 32, stream)
+            torch.cuda.synchronize()
+            ml.append(time.perf_counter() - s0)
+        assert sk.decrypt_uint(F.to_host(mR), 32)[0] == (int(ma[0]) * int(mb[0])) % (1 << 32)
+        mul = {"p50_ms": round(1e3 * float(np.median(ml)), 1), "p99_ms": round(1e3 * float(np.percentile(ml, 99)), 1),
+               "samples": len(ml), "gates": F.fhe_circuit_shape("mul", 32)[0]}
+        log(f"mul32 latency: {mul}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(sk, workloads.AddWorkload().operands()[0], workloads.AddWorkload().operands()[1],
+                           16, args.cpu_sample_gates)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": "bootstrapped gates/sec on 1 MI355X (batched vs plain) + p50/p99 latency per 32-bit mul",
+        "value": round(value, 1), "unit": "gates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 (Torus32) / u64 (Z_p NTT)", "data": "synthetic",
+        "config": workload,
+        "plain": plain, "mul32_latency": mul,
+        "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

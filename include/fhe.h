@@ -204,6 +204,16 @@ int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
 /* Errors and diagnostics.                                                  */
 /* ---------------------------------------------------------------------- */
 
+/* Per-phase device timing, the split of the paper's Table IV (bootstrapping,
+ * key switching).  While enabled, every batched launch pair records HIP
+ * events on the stream it runs on.  fhe_ctx_timing() waits for the recorded
+ * work, returns the totals since the last call (milliseconds of blind-
+ * rotation and key-switch kernels, number of launch pairs, gates) and resets
+ * them.  Any output pointer may be NULL. */
+int fhe_ctx_set_timing(fhe_ctx* ctx, int enable);
+int fhe_ctx_timing(fhe_ctx* ctx, double* blind_rotate_ms, double* key_switch_ms,
+                   uint64_t* launches, uint64_t* gates);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* fhe_last_error(void);
 

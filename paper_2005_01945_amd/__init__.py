@@ -57,6 +57,9 @@ _SIGS = {
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
+    "fhe_ctx_set_timing": (C.c_int, [_vp, C.c_int]),
+    "fhe_ctx_timing": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "fhe_last_error": (C.c_char_p, []),
     "fhe_debug_cmux": (C.c_int, [C.c_int, _vp, C.c_int32, _vp]),
 }
@@ -263,6 +266,17 @@ def fhe_circuit_shape(kind, width, rows=0, cols=0):
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")
     return g.value, lv.value, wd.value
+
+
+def fhe_ctx_set_timing(ctx, enable):
+    _check(lib().fhe_ctx_set_timing(ctx.h, 1 if enable else 0), "fhe_ctx_set_timing")
+
+
+def fhe_ctx_timing(ctx):
+    """(blind_rotate_ms, key_switch_ms, launches, gates) since the last call."""
+    br, ks, n, g = C.c_double(), C.c_double(), C.c_uint64(), C.c_uint64()
+    _check(lib().fhe_ctx_timing(ctx.h, C.byref(br), C.byref(ks), C.byref(n), C.byref(g)), "fhe_ctx_timing")
+    return br.value, ks.value, n.value, g.value
 
 
 def fhe_debug_cmux(bk_i, abar, acc, device=0):

@@ -93,14 +93,36 @@ int ctx_reserve_big(fhe_ctx* ctx, size_t gates) {
     return FHE_OK;
 }
 
+static hipEvent_t take_event(fhe_ctx* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s) {
     if (count == 0) return FHE_OK;
     int rc = ctx_reserve_big(ctx, count);
     if (rc) return rc;
+    fhe_ctx::TimedLaunch tl{{nullptr, nullptr, nullptr}, count};
+    if (ctx->timing) {
+        for (auto& ev : tl.ev)
+            if (!(ev = take_event(ctx))) return set_error(FHE_EDEVICE, "timing event creation failed");
+        (void)hipEventRecord(tl.ev[0], s);
+    }
     hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count, s);
     if (e != hipSuccess) return hip_fail(e, "blind rotation launch");
+    if (ctx->timing) (void)hipEventRecord(tl.ev[1], s);
     e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)count, s);
     if (e != hipSuccess) return hip_fail(e, "key switch launch");
+    if (ctx->timing) {
+        (void)hipEventRecord(tl.ev[2], s);
+        ctx->timed.push_back(tl);
+    }
     return FHE_OK;
 }
 
@@ -181,6 +203,9 @@ extern "C" void fhe_ctx_destroy(fhe_ctx* ctx) {
         DeviceGuard guard(ctx->device);
         (void)hipDeviceSynchronize();
         destroy_circuit_cache(ctx);
+        for (auto& tl : ctx->timed)
+            for (hipEvent_t ev : tl.ev) ctx->event_pool.push_back(ev);
+        for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
         for (void* p : {(void*)ctx->bkd, (void*)ctx->ksk, (void*)ctx->zero_row, (void*)ctx->twf,
                         (void*)ctx->twi, (void*)ctx->big})
             if (p) (void)hipFree(p);
@@ -255,4 +280,36 @@ extern "C" int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, ui
     for (void* p : {(void*)d_twf, (void*)d_twi, (void*)d_bkd, (void*)d_bk, (void*)d_acc})
         if (p) (void)hipFree(p);
     return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_debug_cmux");
+}
+
+extern "C" int fhe_ctx_set_timing(fhe_ctx* ctx, int enable) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_set_timing: null context");
+    ctx->timing = enable != 0;
+    return FHE_OK;
+}
+
+extern "C" int fhe_ctx_timing(fhe_ctx* ctx, double* br_ms, double* ks_ms, uint64_t* launches,
+                              uint64_t* gates) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_timing: null context");
+    DeviceGuard guard(ctx->device);
+    double br = 0, ks = 0;
+    uint64_t g = 0;
+    int rc = FHE_OK;
+    for (auto& tl : ctx->timed) {
+        hipError_t e = hipEventSynchronize(tl.ev[2]);
+        float a = 0, b = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, tl.ev[0], tl.ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, tl.ev[1], tl.ev[2]);
+        if (e != hipSuccess && rc == FHE_OK) rc = hip_fail(e, "fhe_ctx_timing");
+        br += a;
+        ks += b;
+        g += tl.gates;
+        for (hipEvent_t ev : tl.ev) ctx->event_pool.push_back(ev);
+    }
+    if (br_ms) *br_ms = br;
+    if (ks_ms) *ks_ms = ks;
+    if (launches) *launches = ctx->timed.size();
+    if (gates) *gates = g;
+    ctx->timed.clear();
+    return rc;
 }

@@ -26,6 +26,14 @@ struct fhe_ctx {
     size_t big_cap = 0;       // words
     fhe::dev::DeviceKeys keys{};
     fhe::CircuitCache* circuits = nullptr;
+    // per-phase timing: events {before BR, after BR, after KS} per launch pair
+    bool timing = false;
+    struct TimedLaunch {
+        hipEvent_t ev[3];
+        uint64_t gates;
+    };
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace fhe {

@@ -1,0 +1,135 @@
+"""GPU parity of the integer circuits (level-scheduled batched gates) against
+the oracle: bit-exact end to end at sizes the oracle finishes in seconds, and
+at the paper-sized workloads bit-exact on sampled outputs plus decryption
+equal to plaintext arithmetic on every output."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2005_01945_amd as F
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    sk, ck = F.fhe_keygen(0)
+    return sk, F.Context(ck, 0), oracle.Keys(0)
+
+
+def gpu_binary(ctx, fn, ca, cb, count, width):
+    import torch
+    dA, dB = F.to_device(ca), F.to_device(cb)
+    dR = torch.empty_like(dA)
+    fn(ctx, dA, dB, dR, count, width)
+    torch.cuda.synchronize()
+    return F.to_host(dR)
+
+
+@pytest.mark.parametrize("width,count", [(1, 2), (4, 3), (7, 5)])
+def test_add_bit_exact(env, width, count):
+    sk, ctx, K = env
+    a = workloads.uniform_uints(10 + width, count, width)
+    b = workloads.uniform_uints(20 + width, count, width)
+    ca = sk.encrypt_uint(a, width, nonce=100_000)
+    cb = sk.encrypt_uint(b, width, nonce=200_000)
+    log(f"add width={width} count={count}")
+    got = gpu_binary(ctx, F.fhe_add, ca, cb, count, width)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, width), (a + b) % (1 << width))
+    np.testing.assert_array_equal(got, K.add(ca, cb, width))
+
+
+@pytest.mark.parametrize("width,count", [(1, 1), (3, 2), (5, 2)])
+def test_mul_bit_exact(env, width, count):
+    sk, ctx, K = env
+    a = workloads.uniform_uints(30 + width, count, width)
+    b = workloads.uniform_uints(40 + width, count, width)
+    ca = sk.encrypt_uint(a, width, nonce=300_000)
+    cb = sk.encrypt_uint(b, width, nonce=400_000)
+    log(f"mul width={width} count={count}")
+    got = gpu_binary(ctx, F.fhe_mul, ca, cb, count, width)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, width), (a * b) % (1 << width))
+    np.testing.assert_array_equal(got, K.mul(ca, cb, width))
+
+
+@pytest.mark.parametrize("rows,cols,width", [(2, 3, 3), (1, 1, 2)])
+def test_matvec_bit_exact(env, rows, cols, width):
+    import torch
+    sk, ctx, K = env
+    M = workloads.uniform_range(50 + rows, (rows, cols), 0, 1 << width)
+    x = workloads.uniform_range(60 + cols, (cols,), 0, 1 << width)
+    cm = sk.encrypt_uint(M.reshape(-1), width, nonce=500_000)
+    cx = sk.encrypt_uint(x, width, nonce=600_000)
+    dM, dx = F.to_device(cm), F.to_device(cx)
+    dy = torch.empty((rows, width, F.WORDS), dtype=torch.int32, device="cuda")
+    log(f"matvec {rows}x{cols} width={width}")
+    F.fhe_matvec(ctx, dM, dx, dy, rows, cols, width)
+    torch.cuda.synchronize()
+    got = F.to_host(dy)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, width), (M @ x) % (1 << width))
+    np.testing.assert_array_equal(got, K.matvec(cm, cx, rows, cols, width))
+
+
+def test_add16_full_size(env):
+    """1024 pairs of uniform uint16 in one level-scheduled run (the benchmark's
+    launch configuration): every sum decrypts correctly, pair 0 is bit-exact."""
+    sk, ctx, K = env
+    wl = workloads.AddWorkload()
+    a, b = wl.operands()
+    ca = sk.encrypt_uint(a, wl.width, nonce=0)
+    cb = sk.encrypt_uint(b, wl.width, nonce=1 << 40)
+    log("add16 x 1024 pairs")
+    got = gpu_binary(ctx, F.fhe_add, ca, cb, wl.count, wl.width)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (a + b) % (1 << wl.width))
+    log("oracle: pair 0 end to end")
+    np.testing.assert_array_equal(got[0], K.add(ca[:1], cb[:1], wl.width)[0])
+
+
+def test_mul32_full_size_decrypts(env):
+    """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
+    product decrypts correctly."""
+    sk, ctx, K = env
+    wl = workloads.MulWorkload()
+    a, b = wl.operands()
+    ca = sk.encrypt_uint(a, wl.width, nonce=0)
+    cb = sk.encrypt_uint(b, wl.width, nonce=1 << 40)
+    log("mul32 x 256 pairs")
+    got = gpu_binary(ctx, F.fhe_mul, ca, cb, wl.count, wl.width)
+    want = (a.astype(object) * b.astype(object)) % (1 << 32)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, 32).astype(object), want)
+
+
+def test_mul8_in_wide_batch_bit_exact(env):
+    """A 256-pair batch of 8-bit products; pair 0 bit-exact against the oracle."""
+    sk, ctx, K = env
+    a = workloads.uniform_uints(70, 256, 8)
+    b = workloads.uniform_uints(71, 256, 8)
+    ca = sk.encrypt_uint(a, 8, nonce=700_000)
+    cb = sk.encrypt_uint(b, 8, nonce=800_000)
+    log("mul8 x 256 pairs")
+    got = gpu_binary(ctx, F.fhe_mul, ca, cb, 256, 8)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, 8), (a * b) % 256)
+    log("oracle: mul8 pair 0")
+    np.testing.assert_array_equal(got[0], K.mul(ca[:1], cb[:1], 8)[0])
+
+
+def test_matvec8_serving_size_decrypts(env):
+    """The 8x8 8-bit product of the serving mix (10,608 gates)."""
+    import torch
+    sk, ctx, K = env
+    M = workloads.uniform_range(80, (8, 8), 0, 256)
+    x = workloads.uniform_range(81, (8,), 0, 256)
+    cm = sk.encrypt_uint(M.reshape(-1), 8, nonce=900_000)
+    cx = sk.encrypt_uint(x, 8, nonce=990_000)
+    dy = torch.empty((8, 8, F.WORDS), dtype=torch.int32, device="cuda")
+    log("matvec 8x8 8-bit")
+    F.fhe_matvec(ctx, F.to_device(cm), F.to_device(cx), dy, 8, 8, 8)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sk.decrypt_uint(F.to_host(dy), 8), (M @ x) % 256)
