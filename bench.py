@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--mul-samples", type=int, default=5)
     ap.add_argument("--cpu-sample-gates", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -185,22 +187,33 @@ def main():
                 "kernel": "k_blind_rotate", "avg_launch_ms": round(avg_launch_ms, 3),
                 "gates_per_launch": round(gates_per_launch, 1)}
 
+    if args.copy_calibration_mib > 0:
+        src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+
     # plain path: one gate per launch, synchronous
+    plain = None
     a_bits, b_bits = workloads.truth_table_inputs()
     p0 = F.to_device(sk.encrypt_bits(a_bits, nonce=1 << 50))
     p1 = F.to_device(sk.encrypt_bits(b_bits, nonce=(1 << 50) + 100))
     pout = torch.empty_like(p0)
-    for g in range(4):
-        F.fhe_bootstrap_gate_plain(ctx, F.NAND, p0[g], p1[g], pout[g], stream)
     lat = []
-    for _ in range(args.plain_reps):
+    for rep in range(args.plain_reps + 1 if args.plain_reps > 0 else 0):
         for g in range(4):
             s0 = time.perf_counter()
             F.fhe_bootstrap_gate_plain(ctx, F.NAND, p0[g], p1[g], pout[g], stream)
-            lat.append(time.perf_counter() - s0)
-    plain = {"gates_per_s": round(len(lat) / sum(lat), 2), "p50_ms": round(1e3 * float(np.median(lat)), 3),
-             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)}
-    log(f"plain: {plain}")
+            if rep > 0:  # the first round is warmup
+                lat.append(time.perf_counter() - s0)
+    if lat:
+        assert list(sk.decrypt_bits(F.to_host(pout))) == [1, 1, 1, 0]
+        plain = {"gates_per_s": round(len(lat) / sum(lat), 2), "p50_ms": round(1e3 * float(np.median(lat)), 3),
+                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "gates": len(lat)}
+        log(f"plain: {plain}")
 
     # latency of one 32-bit multiplication (one pair, 120 levels)
     mul = None

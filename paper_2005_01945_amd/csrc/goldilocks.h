@@ -1,8 +1,8 @@
 // Arithmetic in Z_p, p = 2^64 - 2^32 + 1, for the exact negacyclic NTT.
 //
-// Values are uint64 words congruent to the element mod p, not necessarily
-// reduced below p ("loose" form); gl_canon() gives the representative in
-// [0, p).  The reductions use 2^64 = 2^32 - 1 and 2^96 = -1 (mod p).
+// Elements are kept canonical (uint64 in [0, p)).  The reductions use
+// 2^64 = 2^32 - 1 and 2^96 = -1 (mod p); carries are detected by comparing
+// a wrapped sum with one of its addends.
 // Usable on the host (twiddle tables) and on gfx950.
 #pragma once
 
@@ -19,36 +19,50 @@ namespace gl {
 constexpr uint64_t P = 0xFFFFFFFF00000001ull;
 constexpr uint64_t EPS = 0xFFFFFFFFull;  // 2^64 mod p
 
-GL_FN uint64_t canon(uint64_t x) { return x >= P ? x - P : x; }
+// Every function below takes and returns canonical values (in [0, p)).
+// Carries are read from the top bits (majority of the operands' and the
+// complemented result's sign bits) and folded back with a multiply-add
+// c * (2^32 - 1) + s, which on gfx950 keeps them out of scalar lane masks.
 
-// x + y for loose x, y.
+GL_FN uint32_t hi32(uint64_t a) { return (uint32_t)(a >> 32); }
+
+// Carry out of the 64-bit sum s = a + b (mod 2^64), as 0 or 1.
+GL_FN uint32_t carry64(uint64_t a, uint64_t b, uint64_t s) {
+    const uint32_t a1 = hi32(a), b1 = hi32(b), s1 = hi32(s);
+    return ((a1 & b1) | ((a1 | b1) & ~s1)) >> 31;
+}
+
+// x mod p for any 64-bit x: x >= p exactly when x + EPS wraps.
+GL_FN uint64_t canon(uint64_t x) {
+    const uint64_t t = x + EPS;
+    return carry64(x, EPS, t) ? t : x;
+}
+
+// x + y: t = x + (y + EPS) wraps exactly when x + y >= p, and then t is the
+// reduced sum; otherwise the sum is t - EPS.
 GL_FN uint64_t add(uint64_t x, uint64_t y) {
-    uint64_t s = x + y;
-    uint64_t c = (s < x) ? EPS : 0;  // 2^64 wrapped away: add it back as EPS
-    s += c;
-    s += (s < c) ? EPS : 0;          // second wrap (only when s >= p)
-    return s;
+    const uint64_t y2 = y + EPS;  // < 2^64 because y < p
+    const uint64_t t = x + y2;
+    return (uint64_t)carry64(x, y2, t) * EPS + (t - EPS);
 }
 
-// x - y for loose x, y.
+// x - y: on borrow add p, i.e. subtract EPS modulo 2^64.
 GL_FN uint64_t sub(uint64_t x, uint64_t y) {
-    uint64_t d = x - y;
-    uint64_t b = (x < y) ? EPS : 0;  // 2^64 borrowed: remove it as EPS
-    uint64_t d2 = d - b;
-    d2 -= (d < b) ? EPS : 0;
-    return d2;
+    const uint64_t d = x - y;
+    return d - (uint64_t)(x < y) * EPS;
 }
 
-// (hi * 2^64 + lo) mod p, loose.  hi = hh*2^32 + hl:
+// (hi * 2^64 + lo) mod p for any hi, lo.  hi = hh*2^32 + hl:
 // hh*2^96 = -hh and hl*2^64 = hl*(2^32 - 1).
 GL_FN uint64_t reduce128(uint64_t hi, uint64_t lo) {
-    const uint64_t hh = hi >> 32, hl = hi & 0xFFFFFFFFull;
+    const uint64_t hh = hi >> 32;
+    const uint32_t hl = (uint32_t)hi;
     uint64_t t0 = lo - hh;
-    if (lo < hh) t0 -= EPS;          // lo - hh + 2^64 >= 2^64 - 2^32: no second wrap
-    const uint64_t t1 = (hl << 32) - hl;
-    uint64_t r = t0 + t1;
-    if (r < t1) r += EPS;            // t0 + t1 - 2^64 < t1 <= 2^64 - 2^33 + 1
-    return r;
+    // borrow iff lo < hh (< 2^32); then lo - hh + 2^64 >= 2^64 - 2^32, no second wrap
+    t0 -= (uint64_t)((~hi32(lo) & hi32(t0)) >> 31) * EPS;
+    const uint64_t t1 = (uint64_t)hl * EPS;  // <= (2^32 - 1)^2 < p
+    const uint64_t r = t0 + t1;              // a wrap leaves r < t1, + EPS cannot wrap again
+    return canon((uint64_t)carry64(t0, t1, r) * EPS + r);
 }
 
 // 64 x 64 -> 128-bit product from four 32 x 32 -> 64 partial products.
@@ -68,36 +82,25 @@ GL_FN uint64_t mul(uint64_t x, uint64_t y) {
     return reduce128(hi, lo);
 }
 
-// x * 2^S for a compile-time S in [0, 96), by limb shifts only:
-// x << S spans five 32-bit limbs w0..w4, and
-//   w0 + w1 2^32 + w2 2^64 + w3 2^96 + w4 2^128
-//     = (w1:w0) + w2 (2^32 - 1) - (w4:w3)   (mod p).
+// x * 2^S for a compile-time S in [0, 96), by shifts: with the 32-bit limbs
+// w0..w4 of x << S,  x 2^S = (w1:w0) + w2 (2^32 - 1) - (w4:w3)  (mod p).
 template <int S>
 GL_FN uint64_t mul_pow2(uint64_t x) {
     static_assert(S >= 0 && S < 96, "shift out of range");
     if constexpr (S == 0) {
         return x;
-    } else {
-        constexpr int q = S / 32, r = S % 32;
-        const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
-        uint32_t u0, u1, u2;
-        if constexpr (r == 0) {
-            u0 = x0; u1 = x1; u2 = 0;
+    } else if constexpr (S < 64) {
+        const uint64_t A = x << S;                                      // (w1:w0)
+        const uint64_t T = (uint64_t)(uint32_t)(x >> (64 - S)) * EPS + A;  // + w2 (2^32 - 1)
+        const uint64_t R = canon((uint64_t)(T < A) * EPS + T);          // one wrap at most
+        if constexpr (S <= 32) {
+            return R;                                                   // w3 = w4 = 0
         } else {
-            u0 = x0 << r;
-            u1 = (x1 << r) | (x0 >> (32 - r));
-            u2 = x1 >> (32 - r);
+            return sub(R, (uint32_t)(x >> (96 - S)));                   // - w3
         }
-        uint32_t w[5] = {0, 0, 0, 0, 0};
-        w[q] = u0;
-        w[q + 1] = u1;
-        w[q + 2] = u2;
-        const uint64_t lo = ((uint64_t)w[1] << 32) | w[0];
-        const uint64_t mid = ((uint64_t)w[2] << 32) - w[2];   // w2 * (2^32 - 1)
-        const uint64_t top = ((uint64_t)w[4] << 32) | w[3];
-        uint64_t s = lo + mid;
-        if (s < mid) s += EPS;                                 // no second wrap (mid <= p - 2^32)
-        return sub(s, top);
+    } else {
+        const uint64_t B = (uint64_t)(uint32_t)(x << (S - 64)) * EPS;   // w2 (2^32 - 1) < p
+        return sub(B, x >> (96 - S));                                   // - (w4:w3), < 2^63
     }
 }
 
@@ -116,8 +119,8 @@ GL_FN uint64_t pow(uint64_t b, uint64_t e) {
     uint64_t r = 1;
     b = canon(b);
     while (e) {
-        if (e & 1) r = canon(mul(r, b));
-        b = canon(mul(b, b));
+        if (e & 1) r = mul(r, b);
+        b = mul(b, b);
         e >>= 1;
     }
     return r;

@@ -6,9 +6,10 @@
 // product is below 4 * 1024 * 2^9 * 2^31 = 2^52 < p/2 in magnitude and lifts
 // back to Z/2^32 exactly: results equal the schoolbook definition bit for bit.
 //
-// Work layout: one wavefront (64 lanes) bootstraps one gate.  Lane
-// l = 32h + t (half h, t < 32) keeps, for polynomial h of the accumulator,
-// coefficients m = t + 32*q in register q (q < 32).  A 1024-point negacyclic
+// Work layout: one wavefront (64 lanes) bootstraps one gate; its accumulator
+// (two polynomials of 1024 uint32) lives in LDS.  Lane l = 32h + t (half h,
+// t < 32) transforms polynomial data of coefficients m = t + 32*q, held in
+// register q (q < 32).  A 1024-point negacyclic
 // NTT is split 32 x 32: a 32-point negacyclic transform in registers over q
 // (root psi^32 = 8, so every twiddle is a power of two: shifts only), one
 // general twiddle psi^(t(2j+1)) per value, a transpose through LDS, and a
@@ -134,6 +135,10 @@ __device__ __forceinline__ void ntt32_neg_inv(uint64_t (&x)[32]) {
     });
 }
 
+// Scheduling fence: keeps the compiler from hoisting the loads of later
+// chunks above it, which bounds the registers held by loads in flight.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 // Orders the wave's LDS traffic: LDS operations of one wavefront execute in
 // issue order, so a compiler-level barrier is all a wave-private exchange
 // needs.
@@ -143,40 +148,55 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 32 x 32 transpose of 64-bit values through this half's 4 KB tile of
+// 32-bit words, one word of each value at a time.  Element (row, col) sits at
+// row*32 + (col ^ row), which keeps both the row writes and the column reads
+// free of bank conflicts.  Before: register k holds (row wr(k), col t); after:
+// register k holds (row t, col rd(k)).
+template <class WR, class RD>
+__device__ __forceinline__ void transpose32(uint64_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
+    uint32_t lo[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) tile[wr(k) * 32 + (t ^ wr(k))] = (uint32_t)x[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) lo[k] = tile[t * 32 + (rd(k) ^ t)];
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) tile[wr(k) * 32 + (t ^ wr(k))] = (uint32_t)(x[k] >> 32);
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) x[k] = ((uint64_t)tile[t * 32 + (rd(k) ^ t)] << 32) | lo[k];
+    wave_lds_sync();
+}
+
 // Full 1024-point forward negacyclic NTT of this half's polynomial.
-// xb: this half's 32 x 32 LDS tile; element (row, col) at row*32 + (col ^ row).
-__device__ __forceinline__ void ntt1024_fwd(uint64_t (&x)[32], uint64_t* xb,
+__device__ __forceinline__ void ntt1024_fwd(uint64_t (&x)[32], uint32_t* tile,
                                             const uint64_t* twf, int t) {
     ntt32_neg_fwd(x);
 #pragma unroll
-    for (int q = 0; q < 32; ++q) x[q] = gl::mul(x[q], twf[q * 32 + t]);
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-        const int row = brv5(q);
-        xb[row * 32 + (t ^ row)] = x[q];
+        for (int q = 8 * c; q < 8 * c + 8; ++q) x[q] = gl::mul(x[q], twf[q * 32 + t]);
     }
-    wave_lds_sync();
-#pragma unroll
-    for (int r = 0; r < 32; ++r) x[r] = xb[t * 32 + (r ^ t)];
-    wave_lds_sync();
+    sched_fence();
+    transpose32(x, tile, t, [](int q) { return brv5(q); }, [](int r) { return r; });
     ntt32_cyc_fwd(x);
 }
 
 // Inverse of ntt1024_fwd including N^-1 (folded in twi).
-__device__ __forceinline__ void ntt1024_inv(uint64_t (&x)[32], uint64_t* xb,
+__device__ __forceinline__ void ntt1024_inv(uint64_t (&x)[32], uint32_t* tile,
                                             const uint64_t* twi, int t) {
     ntt32_cyc_inv(x);
 #pragma unroll
-    for (int r = 0; r < 32; ++r) x[r] = gl::mul(x[r], twi[r * 32 + t]);
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
 #pragma unroll
-    for (int r = 0; r < 32; ++r) xb[r * 32 + (t ^ r)] = x[r];
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 32; ++q) {
-        const int col = brv5(q);
-        x[q] = xb[t * 32 + (col ^ t)];
+        for (int r = 8 * c; r < 8 * c + 8; ++r) x[r] = gl::mul(x[r], twi[r * 32 + t]);
     }
-    wave_lds_sync();
+    sched_fence();
+    transpose32(x, tile, t, [](int r) { return r; }, [](int q) { return brv5(q); });
     ntt32_neg_inv(x);
 }
 
@@ -192,63 +212,77 @@ __device__ __forceinline__ uint64_t partner64(uint64_t v, int h) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Shared-memory footprint of one block: twiddles plus one 16 KB tile pair
-// per wave.
+// Per-wave LDS: the accumulator (two polynomials of 1024 words) and one
+// 32 x 32 transpose tile of 32-bit words per half.  16 KB.
+struct WaveLds {
+    uint32_t acc[2][1024];
+    uint32_t tile[2][32 * 32];
+};
+
+// Shared-memory footprint of one block: twiddles plus one WaveLds per wave
+// (80 KB: two blocks fit a CU's 160 KB, i.e. two waves per SIMD).
 struct BlockLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
-    uint64_t tile[kWavesPerBlock][2][32 * 32];
+    WaveLds w[kWavesPerBlock];
 };
 
-// One CMux step on this wave's accumulator (acc: lane (h, t) register q =
-// coefficient t + 32q of polynomial h).  bk_i: BK_i in the kernel layout
-// [hp][q][sel][64 lanes].
-__device__ __forceinline__ void cmux_step(uint32_t (&acc)[32], int ai, const uint64_t* __restrict__ bk_i,
-                                          uint64_t* tile /* 2 x 1024 u64 */, const uint64_t* twf,
-                                          const uint64_t* twi, int lane) {
+// Pass hp of a CMux step: D = X^ai ACC_hp - ACC_hp, this half's gadget digit
+// of it (half h extracts digit h), its forward NTT, then the multiply-
+// accumulate against BK_i rows (2hp + h) and (2hp + 1 - h), column h.
+// bk_i: BK_i in the kernel layout [hp][q][sel][64 lanes].
+template <int HP>
+__device__ __forceinline__ void cmux_pass(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
+                                          const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
-    uint64_t* xb = tile + h * 1024;
-    uint32_t* accs = reinterpret_cast<uint32_t*>(tile);  // 1024 words, reused
-    const int shift = 22 - 10 * h;                        // digit h of the gadget
-    uint64_t mac[32];
+    const int shift = 22 - 10 * h;
+    const uint32_t* a = W.acc[HP];
     uint64_t x[32];
-
 #pragma unroll
-    for (int hp = 0; hp < 2; ++hp) {
-        // Publish polynomial hp of the accumulator, then form
-        // D = X^ai ACC_hp - ACC_hp and this half's digit of every coefficient.
-        if (h == hp) {
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
 #pragma unroll
-            for (int q = 0; q < 32; ++q) accs[t + 32 * q] = acc[q];
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
+        for (int q = 8 * c; q < 8 * c + 8; ++q) {
             const int m = t + 32 * q;
             const int s = (m - ai) & 2047;
-            const uint32_t v = accs[s & 1023];
+            const uint32_t v = a[s & 1023];
             const uint32_t rot = (s & 1024) ? 0u - v : v;
-            const uint32_t D = rot - accs[m];
+            const uint32_t D = rot - a[m];
             const int32_t dg = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
             x[q] = gl::from_i64(dg);
         }
-        wave_lds_sync();
-        ntt1024_fwd(x, xb, twf, t);
-        // Multiply-accumulate against BK_i rows (2hp + h) and (2hp + 1 - h),
-        // column h, in the NTT domain.
-        const uint64_t* bkp = bk_i + (size_t)hp * (32 * 2 * 64) + lane;
+    }
+    sched_fence();
+    ntt1024_fwd(x, W.tile[h], twf, t);
+    const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
+    for (int c = 0; c < 8; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int q = 4 * c; q < 4 * c + 4; ++q) {
             const uint64_t other = partner64(x[q], h);
             const uint64_t b_own = bkp[(q * 2 + 0) * 64];
             const uint64_t b_oth = bkp[(q * 2 + 1) * 64];
             const uint64_t v = gl::add(gl::mul(x[q], b_own), gl::mul(other, b_oth));
-            mac[q] = hp == 0 ? v : gl::add(mac[q], v);
+            mac[q] = HP == 0 ? v : gl::add(mac[q], v);
         }
     }
-    ntt1024_inv(mac, xb, twi, t);
+    sched_fence();
+}
+
+// One CMux step on this wave's accumulator W.acc:
+//   ACC += BK_i [x] (X^ai ACC - ACC).
+__device__ __forceinline__ void cmux_step(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
+                                          const uint64_t* twf, const uint64_t* twi, int lane) {
+    const int h = lane >> 5, t = lane & 31;
+    uint64_t mac[32];
+    cmux_pass<0>(W, ai, bk_i, twf, lane, mac);
+    cmux_pass<1>(W, ai, bk_i, twf, lane, mac);
+    ntt1024_inv(mac, W.tile[h], twi, t);
+    uint32_t* mine = W.acc[h];
 #pragma unroll
-    for (int q = 0; q < 32; ++q) acc[q] += gl::lift32(gl::canon(mac[q]));
+    for (int q = 0; q < 32; ++q) mine[t + 32 * q] += gl::lift32(mac[q]);
+    wave_lds_sync();
 }
 
 // Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding).
@@ -304,7 +338,7 @@ __device__ __forceinline__ void load_twiddles(BlockLds& S, const uint64_t* twf, 
 
 // Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
 // sample extraction.  One wave per gate, four gates per block.
-__global__ __launch_bounds__(kBlockThreads) void k_blind_rotate(DeviceKeys K, GateIO io,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_blind_rotate(DeviceKeys K, GateIO io,
                                                                 uint32_t* __restrict__ big,
                                                                 uint32_t count) {
     __shared__ BlockLds S;
@@ -336,7 +370,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_blind_rotate(DeviceKeys K, Ga
     const int bbar = __builtin_amdgcn_readlane(ab[7], NLWE - 448);
 
     // ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... + X^(N-1)).
-    uint32_t acc[32];
+    WaveLds& W = S.w[wave];
     {
         const int c = (2 * N - bbar) & (2 * N - 1);
         const int cm = c & (N - 1);
@@ -345,37 +379,29 @@ __global__ __launch_bounds__(kBlockThreads) void k_blind_rotate(DeviceKeys K, Ga
         for (int q = 0; q < 32; ++q) {
             const int m = t + 32 * q;
             const uint32_t sgn = (m >= cm) ? neg : 1u - neg;  // 1 -> -mu
-            acc[q] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
+            W.acc[h][m] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
         }
     }
+    wave_lds_sync();
 
-    uint64_t* tile = &S.tile[wave][0][0];
+    // Blind rotation.  abar_i = 0 would give D = 0 and leave ACC unchanged,
+    // so every step runs unconditionally.
     const uint64_t* bk = K.bkd;
 #pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const int lim = (NLWE - 64 * k) < 64 ? (NLWE - 64 * k) : 64;
-#pragma unroll 1
-        for (int l = 0; l < lim; ++l) {
-            const int ai = __builtin_amdgcn_readlane(ab[0], l);
-            if (ai != 0) cmux_step(acc, ai, bk, tile, S.twf, S.twi, lane);
-            bk += 2 * 32 * 2 * 64;
-        }
+    for (int i = 0; i < NLWE; ++i) {
+        const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
+        cmux_step(W, ai, bk, S.twf, S.twi, lane);
+        bk += 2 * 32 * 2 * 64;
+        if ((i & 63) == 63) {
 #pragma unroll
-        for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+            for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+        }
     }
 
     // Sample extraction of coefficient 0: a'_0 = a_0, a'_m = -a_(N-m), b' = b_0.
     uint32_t* o = big + (size_t)g * (N + 1);
-    if (h == 0) {
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const int m = t + 32 * q;
-            if (m == 0) o[0] = acc[q];
-            else o[N - m] = 0u - acc[q];
-        }
-    } else if (t == 0) {
-        o[N] = acc[0];
-    }
+    for (int m = lane; m < N; m += 64) o[m == 0 ? 0 : N - m] = m == 0 ? W.acc[0][0] : 0u - W.acc[0][m];
+    if (lane == 0) o[N] = W.acc[1][0];
 }
 
 // Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
@@ -424,7 +450,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __
                                                               const uint64_t* __restrict__ twf,
                                                               uint32_t npolys) {
     __shared__ uint64_t stw[32 * 32];
-    __shared__ uint64_t tiles[kWavesPerBlock][2][32 * 32];
+    __shared__ uint32_t tiles[kWavesPerBlock][2][32 * 32];
     for (int k = threadIdx.x; k < 1024; k += kBlockThreads) stw[k] = twf[k];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -447,19 +473,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __
 __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bkd_i,
                                                    int32_t abar, uint32_t* __restrict__ accg) {
     __shared__ uint64_t stw[2][32 * 32];
-    __shared__ uint64_t tile[2][32 * 32];
+    __shared__ WaveLds W;
     for (int k = threadIdx.x; k < 1024; k += 64) {
         stw[0][k] = K.twf[k];
         stw[1][k] = K.twi[k];
     }
+    for (int k = threadIdx.x; k < 2 * N; k += 64) W.acc[k / N][k % N] = accg[k];
     __syncthreads();
-    const int lane = threadIdx.x, h = lane >> 5, t = lane & 31;
-    uint32_t acc[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) acc[q] = accg[h * N + t + 32 * q];
-    cmux_step(acc, abar, bkd_i, &tile[0][0], stw[0], stw[1], lane);
-#pragma unroll
-    for (int q = 0; q < 32; ++q) accg[h * N + t + 32 * q] = acc[q];
+    cmux_step(W, abar, bkd_i, stw[0], stw[1], threadIdx.x);
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * N; k += 64) accg[k] = W.acc[k / N][k % N];
 }
 
 }  // namespace
