@@ -87,6 +87,76 @@ def cpu_baseline(sk, a, b, width, sample_gates):
                       f"{dt:.1f} s on {threads} threads; per-gate work is identical on every level"}
 
 
+JOB_GATES = None
+
+
+def serving_leg(F, sk, ctx, rate_gates_per_s, n_jobs, budget_bytes, seed=3):
+    """Poisson stream of mixed jobs (single gates, add16, add32, mul32, 8x8
+    8-bit matvec) offered at rate_gates_per_s; every job is checked against
+    plaintext arithmetic after the run."""
+    import torch
+    import workloads
+    kinds = {"gate": (F.FHE_JOB_GATE, 1, 1), "add16": (F.FHE_JOB_ADD, 16, None), "add32": (F.FHE_JOB_ADD, 32, None),
+             "mul32": (F.FHE_JOB_MUL, 32, None), "matvec8": (F.FHE_JOB_MATVEC, 8, None)}
+    gates_of = {"gate": 1, "add16": F.fhe_circuit_shape("add", 16)[0], "add32": F.fhe_circuit_shape("add", 32)[0],
+                "mul32": F.fhe_circuit_shape("mul", 32)[0], "matvec8": F.fhe_circuit_shape("matvec", 8, 8, 8)[0]}
+    mean_gates = sum(p * gates_of[k] for k, p in zip(workloads.JOB_KINDS, workloads.JOB_MIX))
+    jobs = workloads.job_stream(seed, n_jobs, rate_gates_per_s / mean_gates)
+    prepared = []
+    nonce = 1 << 56
+    for j in jobs:
+        kind, w, _ = kinds[j.kind]
+        if j.kind == "gate":
+            a = sk.encrypt_bits(j.a, nonce=nonce); b = sk.encrypt_bits(j.b, nonce=nonce + 1); nonce += 2
+            shape, rows, cols = (1, F.WORDS), 0, 0
+            a_, b_ = int(j.a[0]), int(j.b[0])
+            want = [[a_ & b_, 1 - (a_ & b_), a_ | b_, 1 - (a_ | b_), a_ ^ b_, 1 - (a_ ^ b_),
+                     (1 - a_) & b_, a_ & (1 - b_), (1 - a_) | b_, a_ | (1 - b_)][j.op]]
+        elif j.kind == "matvec8":
+            a = sk.encrypt_uint(j.a.reshape(-1), w, nonce=nonce); nonce += 64 * w
+            b = sk.encrypt_uint(j.b, w, nonce=nonce); nonce += 8 * w
+            shape, rows, cols = (8, w, F.WORDS), 8, 8
+            want = list((j.a @ j.b) % (1 << w))
+        else:
+            a = sk.encrypt_uint(j.a, w, nonce=nonce); b = sk.encrypt_uint(j.b, w, nonce=nonce + w); nonce += 2 * w
+            shape, rows, cols = (w, F.WORDS), 0, 0
+            x, y = int(j.a[0]), int(j.b[0])
+            want = [((x + y) if kind == F.FHE_JOB_ADD else (x * y)) % (1 << w)]
+        prepared.append(dict(j=j, kind=kind, w=w, rows=rows, cols=cols, da=F.to_device(a), db=F.to_device(b),
+                             out=torch.zeros(shape, dtype=torch.int32, device="cuda"), want=want))
+    torch.cuda.synchronize()
+    srv = F.Server(ctx, budget_bytes)
+    t0 = time.perf_counter()
+    tickets = []
+    for p in prepared:
+        delay = p["j"].arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(F.fhe_serve_submit(srv, p["kind"], p["da"], p["db"], p["out"], op=p["j"].op,
+                                          width=p["w"], rows=p["rows"], cols=p["cols"]))
+    for t in tickets:
+        F.fhe_serve_wait(srv, t, 1200)
+    t1 = time.perf_counter()
+    stats = F.fhe_serve_stats(srv)
+    lat = {}
+    bad = 0
+    for p, t in zip(prepared, tickets):
+        st, ms = F.fhe_serve_poll(srv, t)
+        lat.setdefault(p["j"].kind, []).append(ms)
+        host = F.to_host(p["out"])
+        dec = sk.decrypt_bits(host) if p["kind"] == F.FHE_JOB_GATE else sk.decrypt_uint(host, p["w"])
+        bad += list(dec) != list(p["want"])
+    srv.close()
+    if bad:
+        raise SystemExit(f"bench: {bad} served jobs decrypted wrongly")
+    total_gates = sum(gates_of[p["j"].kind] for p in prepared)
+    return {"jobs": len(prepared), "gates": total_gates, "offered_gates_per_s": round(rate_gates_per_s, 1),
+            "served_gates_per_s": round(total_gates / (t1 - t0), 1), "wall_s": round(t1 - t0, 2),
+            "launches": stats["launches"], "hbm_budget_bytes": budget_bytes,
+            "latency_ms": {k: {"p50": round(float(np.percentile(v, 50)), 1), "p99": round(float(np.percentile(v, 99)), 1),
+                                "n": len(v)} for k, v in sorted(lat.items())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +167,11 @@ def main():
     ap.add_argument("--mul-samples", type=int, default=5)
     ap.add_argument("--cpu-sample-gates", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=300,
+                    help="jobs in the serving leg (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load of the serving leg as a fraction of the batched throughput")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -236,6 +311,13 @@ def main():
                "samples": len(ml), "gates": F.fhe_circuit_shape("mul", 32)[0]}
         log(f"mul32 latency: {mul}")
 
+    serving = None
+    if args.serve_jobs > 0:
+        log(f"serving: {args.serve_jobs} jobs at {args.serve_load:.2f} x {value:.0f} gates/s")
+        serving = serving_leg(F, sk, ctx, args.serve_load * value, args.serve_jobs,
+                              int(args.serve_budget_gib * (1 << 30)))
+        log(f"serving: {serving}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -249,7 +331,7 @@ def main():
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32 (Torus32) / u64 (Z_p NTT)", "data": "synthetic",
         "config": workload,
-        "plain": plain, "mul32_latency": mul,
+        "plain": plain, "mul32_latency": mul, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -201,6 +201,66 @@ int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 
 /* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of jobs on one context.                     */
+/* A worker thread owns the context while the server exists (no other call */
+/* may use that context meanwhile).  Each tick it admits queued jobs, in    */
+/* arrival order, whose samples (inputs and every gate output) fit the pool */
+/* left under the HBM budget; runs the next circuit level of every running */
+/* job as one batched launch pair; and retires finished jobs, copying their */
+/* outputs to the caller's buffer.  Jobs that arrive while a tick runs join */
+/* the next tick.  Results do not depend on the mix (each gate is computed  */
+/* exactly, independently of the others in its launch).                      */
+/* ---------------------------------------------------------------------- */
+typedef struct fhe_server fhe_server;
+
+typedef enum { FHE_JOB_GATE = 0, FHE_JOB_ADD = 1, FHE_JOB_MUL = 2, FHE_JOB_MATVEC = 3 } fhe_job_kind;
+
+/* One job.  Buffers are DEVICE memory owned by the caller; inputs must be
+ * written (their stream synchronized) before submission and stay valid, and
+ * `out` is written when the job reaches FHE_JOB_DONE.
+ *   GATE:   in0, in1 [1][n+1], op = gate code, out [1][n+1]
+ *   ADD/MUL: in0, in1, out [width][n+1] (one integer, LSB first)
+ *   MATVEC: in0 = M [rows][cols][width][n+1], in1 = x [cols][width][n+1],
+ *           out = y [rows][width][n+1]                                        */
+typedef struct {
+    uint32_t kind, op, width, rows, cols;
+    const uint32_t* in0;
+    const uint32_t* in1;
+    uint32_t* out;
+} fhe_job;
+
+enum { FHE_JOB_QUEUED = 0, FHE_JOB_RUNNING = 1, FHE_JOB_DONE = 2, FHE_JOB_CANCELLED = 3, FHE_JOB_FAILED = 4 };
+
+/* Creates a server whose job pool may use hbm_budget_bytes of device memory
+ * (allocated at once; 2,004 bytes per sample).  FHE_EINVAL below one gate
+ * job, FHE_ENOMEM if the device cannot hold the pool. */
+int fhe_serve_create(fhe_ctx* ctx, size_t hbm_budget_bytes, fhe_server** out);
+
+/* Queues a job and returns its ticket.  FHE_EBUSY if the job alone needs more
+ * samples than the whole budget (it could never be admitted). */
+int fhe_serve_submit(fhe_server* srv, const fhe_job* job, uint64_t* ticket);
+
+/* State of a job (FHE_JOB_*) and, once done, its latency from submission to
+ * completion in milliseconds (-1 before).  Returns FHE_ECANCELED or the
+ * job's error code for cancelled or failed jobs. */
+int fhe_serve_poll(fhe_server* srv, uint64_t ticket, int* state, double* latency_ms);
+
+/* Blocks until the job is done, cancelled or failed, or timeout_s elapses
+ * (FHE_EBUSY). */
+int fhe_serve_wait(fhe_server* srv, uint64_t ticket, double timeout_s);
+
+/* Cancels a queued or running job; its pool samples are freed at the next
+ * tick and its output buffer is left unspecified. */
+int fhe_serve_cancel(fhe_server* srv, uint64_t ticket);
+
+/* Counters since creation (any pointer may be NULL). */
+int fhe_serve_stats(fhe_server* srv, uint64_t* jobs_done, uint64_t* gates_done, uint64_t* launches,
+                    uint64_t* pool_bytes_in_use, uint64_t* jobs_waiting);
+
+/* Cancels what is left, stops the worker and frees the pool. */
+void fhe_serve_destroy(fhe_server* srv);
+
+/* ---------------------------------------------------------------------- */
 /* Errors and diagnostics.                                                  */
 /* ---------------------------------------------------------------------- */
 

@@ -60,6 +60,14 @@ _SIGS = {
     "fhe_ctx_set_timing": (C.c_int, [_vp, C.c_int]),
     "fhe_ctx_timing": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "fhe_serve_create": (C.c_int, [_vp, C.c_size_t, C.POINTER(_vp)]),
+    "fhe_serve_submit": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint64)]),
+    "fhe_serve_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "fhe_serve_wait": (C.c_int, [_vp, C.c_uint64, C.c_double]),
+    "fhe_serve_cancel": (C.c_int, [_vp, C.c_uint64]),
+    "fhe_serve_stats": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "fhe_serve_destroy": (None, [_vp]),
     "fhe_last_error": (C.c_char_p, []),
     "fhe_debug_cmux": (C.c_int, [C.c_int, _vp, C.c_int32, _vp]),
 }
@@ -277,6 +285,63 @@ def fhe_ctx_timing(ctx):
     br, ks, n, g = C.c_double(), C.c_double(), C.c_uint64(), C.c_uint64()
     _check(lib().fhe_ctx_timing(ctx.h, C.byref(br), C.byref(ks), C.byref(n), C.byref(g)), "fhe_ctx_timing")
     return br.value, ks.value, n.value, g.value
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC = range(4)
+FHE_JOB_QUEUED, FHE_JOB_RUNNING, FHE_JOB_DONE, FHE_JOB_CANCELLED, FHE_JOB_FAILED = range(5)
+
+
+class fhe_job(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("op", C.c_uint32), ("width", C.c_uint32), ("rows", C.c_uint32),
+                ("cols", C.c_uint32), ("in0", _vp), ("in1", _vp), ("out", _vp)]
+
+
+class Server:
+    """fhe_server: continuous batching of jobs on one context."""
+
+    def __init__(self, ctx, hbm_budget_bytes):
+        h = _vp()
+        _check(lib().fhe_serve_create(ctx.h, hbm_budget_bytes, C.byref(h)), "fhe_serve_create")
+        self.h, self.ctx = h.value, ctx
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fhe_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def fhe_serve_submit(srv, kind, in0, in1, out, op=0, width=0, rows=0, cols=0):
+    j = fhe_job(kind, op, width, rows, cols, _dev(in0), _dev(in1), _dev(out))
+    t = C.c_uint64()
+    _check(lib().fhe_serve_submit(srv.h, C.byref(j), C.byref(t)), "fhe_serve_submit")
+    return t.value
+
+
+def fhe_serve_poll(srv, ticket):
+    """(state, latency_ms); raises for cancelled or failed jobs."""
+    st, lat = C.c_int(), C.c_double()
+    _check(lib().fhe_serve_poll(srv.h, ticket, C.byref(st), C.byref(lat)), "fhe_serve_poll")
+    return st.value, lat.value
+
+
+def fhe_serve_wait(srv, ticket, timeout_s=600.0):
+    _check(lib().fhe_serve_wait(srv.h, ticket, timeout_s), "fhe_serve_wait")
+
+
+def fhe_serve_cancel(srv, ticket):
+    _check(lib().fhe_serve_cancel(srv.h, ticket), "fhe_serve_cancel")
+
+
+def fhe_serve_stats(srv):
+    v = [C.c_uint64() for _ in range(5)]
+    _check(lib().fhe_serve_stats(srv.h, *[C.byref(x) for x in v]), "fhe_serve_stats")
+    return dict(zip(["jobs_done", "gates_done", "launches", "pool_bytes_in_use", "jobs_waiting"], [x.value for x in v]))
 
 
 def fhe_debug_cmux(bk_i, abar, acc, device=0):

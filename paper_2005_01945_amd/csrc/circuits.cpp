@@ -25,27 +25,12 @@
 #include <tuple>
 
 #include "fhe_internal.h"
+#include "circuit_ir.h"
 #include "runtime.h"
 
 namespace fhe {
 
 namespace {
-
-enum Kind { kAdd = 0, kMul = 1, kMatvec = 2 };
-
-struct Gate {
-    uint8_t op;
-    uint32_t in0, in1, out;
-};
-
-// One instance of a circuit over local wire ids: [0, na) first operand,
-// [na, na+nb) second operand, then one wire per gate output.
-struct Circuit {
-    uint32_t na = 0, nb = 0;
-    std::vector<Gate> gates;
-    std::vector<uint32_t> outputs;
-    uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
-};
 
 class Builder {
   public:
@@ -103,7 +88,9 @@ class Builder {
     }
 };
 
-std::vector<uint32_t> iota_wires(uint32_t first, uint32_t count) {
+}  // namespace
+
+static std::vector<uint32_t> iota_wires(uint32_t first, uint32_t count) {
     std::vector<uint32_t> v(count);
     for (uint32_t k = 0; k < count; ++k) v[k] = first + k;
     return v;
@@ -141,8 +128,6 @@ std::vector<uint32_t> asap_levels(const Circuit& c, uint32_t* depth) {
     *depth = d;
     return glev;
 }
-
-}  // namespace
 
 // A scheduled, device-resident plan for (kind, width, rows, cols, count).
 struct Plan {

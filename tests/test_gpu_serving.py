@@ -1,0 +1,138 @@
+"""Serving (continuous batching): every job's output is byte-identical alone
+and in a mix, decrypts to the plaintext result, and admission respects the
+HBM budget (queueing when full, refusing what can never fit)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2005_01945_amd as F
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    sk, ck = F.fhe_keygen(0)
+    return sk, F.Context(ck, 0)
+
+
+def make_jobs(sk):
+    """A small mix: two gates, an add16, an add32, a mul8 and a 2x3 4-bit matvec."""
+    import torch
+    jobs = []
+    nonce = 3_000_000
+    for k, op in enumerate([F.NAND, F.XOR]):
+        a = sk.encrypt_bits([k & 1], nonce=nonce); nonce += 1
+        b = sk.encrypt_bits([1], nonce=nonce); nonce += 1
+        jobs.append(dict(kind=F.FHE_JOB_GATE, op=op, a=a, b=b, shape=(1, F.WORDS),
+                         want=[[1 - (k & 1), (k & 1) ^ 1][k]], width=1))
+    for kind, w, x, y in [(F.FHE_JOB_ADD, 16, 51234, 40000), (F.FHE_JOB_ADD, 32, 4000000000, 500000000),
+                          (F.FHE_JOB_MUL, 8, 201, 77)]:
+        a = sk.encrypt_uint([x], w, nonce=nonce); nonce += w
+        b = sk.encrypt_uint([y], w, nonce=nonce); nonce += w
+        res = (x + y) % (1 << w) if kind == F.FHE_JOB_ADD else (x * y) % (1 << w)
+        jobs.append(dict(kind=kind, op=0, a=a, b=b, shape=(w, F.WORDS), want=[res], width=w))
+    M = np.array([[3, 9, 15], [7, 1, 12]], np.uint64)
+    v = np.array([5, 11, 2], np.uint64)
+    a = sk.encrypt_uint(M.reshape(-1), 4, nonce=nonce); nonce += 24
+    b = sk.encrypt_uint(v, 4, nonce=nonce); nonce += 12
+    jobs.append(dict(kind=F.FHE_JOB_MATVEC, op=0, a=a, b=b, shape=(2, 4, F.WORDS), want=list((M @ v) % 16),
+                     width=4, rows=2, cols=3))
+    for j in jobs:
+        j["da"], j["db"] = F.to_device(j["a"]), F.to_device(j["b"])
+    torch.cuda.synchronize()
+    return jobs
+
+
+def submit(srv, j, out):
+    return F.fhe_serve_submit(srv, j["kind"], j["da"], j["db"], out, op=j["op"], width=j["width"],
+                              rows=j.get("rows", 0), cols=j.get("cols", 0))
+
+
+def test_alone_equals_mix_and_decrypts(env):
+    import torch
+    sk, ctx = env
+    jobs = make_jobs(sk)
+    srv = F.Server(ctx, 1 << 30)
+    try:
+        alone = []
+        for j in jobs:
+            out = torch.zeros(j["shape"], dtype=torch.int32, device="cuda")
+            log(f"serving alone: kind {j['kind']} width {j['width']}")
+            t = submit(srv, j, out)
+            F.fhe_serve_wait(srv, t, 300)
+            st, lat = F.fhe_serve_poll(srv, t)
+            assert st == F.FHE_JOB_DONE and lat > 0
+            alone.append(F.to_host(out))
+        outs = [torch.zeros(j["shape"], dtype=torch.int32, device="cuda") for j in jobs]
+        log("serving: all jobs in one mix")
+        tickets = [submit(srv, j, o) for j, o in zip(jobs, outs)]
+        for t in tickets:
+            F.fhe_serve_wait(srv, t, 300)
+        for j, o, a in zip(jobs, outs, alone):
+            got = F.to_host(o)
+            np.testing.assert_array_equal(got, a)
+            dec = sk.decrypt_uint(got, j["width"]) if j["kind"] != F.FHE_JOB_GATE else sk.decrypt_bits(got)
+            assert list(dec) == list(j["want"]), (j["kind"], list(dec), j["want"])
+        stats = F.fhe_serve_stats(srv)
+        assert stats["jobs_done"] == 2 * len(jobs) and stats["pool_bytes_in_use"] == 0
+    finally:
+        srv.close()
+    # a served gate is bit-exact with the oracle
+    K = oracle.Keys(0)
+    np.testing.assert_array_equal(alone[0], K.bootstrap([jobs[0]["op"]], jobs[0]["a"], jobs[0]["b"]))
+
+
+def test_small_budget_queues_and_refuses(env):
+    import torch
+    sk, ctx = env
+    jobs = make_jobs(sk)
+    add32 = jobs[3]
+    need = (2 * 32 + F.fhe_circuit_shape("add", 32)[0]) * F.WORDS * 4
+    srv = F.Server(ctx, need + 1000)  # room for one add32 at a time
+    try:
+        outs = [torch.zeros(add32["shape"], dtype=torch.int32, device="cuda") for _ in range(3)]
+        log("serving: three add32 jobs through a budget that holds one")
+        tickets = [submit(srv, add32, o) for o in outs]
+        states = [F.fhe_serve_poll(srv, t)[0] for t in tickets]
+        assert states.count(F.FHE_JOB_RUNNING) <= 1
+        for t in tickets:
+            F.fhe_serve_wait(srv, t, 300)
+        ref = F.to_host(outs[0])
+        for o in outs[1:]:
+            np.testing.assert_array_equal(F.to_host(o), ref)
+        matvec = jobs[-1]
+        with pytest.raises(F.FheError) as e:
+            submit(srv, matvec, torch.zeros(matvec["shape"], dtype=torch.int32, device="cuda"))
+        assert e.value.code == F.FHE_EBUSY
+    finally:
+        srv.close()
+
+
+def test_cancel_queued_job(env):
+    import torch
+    sk, ctx = env
+    jobs = make_jobs(sk)
+    add32 = jobs[3]
+    need = (2 * 32 + F.fhe_circuit_shape("add", 32)[0]) * F.WORDS * 4
+    srv = F.Server(ctx, need + 1000)
+    try:
+        o1 = torch.zeros(add32["shape"], dtype=torch.int32, device="cuda")
+        o2 = torch.zeros(add32["shape"], dtype=torch.int32, device="cuda")
+        t1 = submit(srv, add32, o1)
+        t2 = submit(srv, add32, o2)
+        F.fhe_serve_cancel(srv, t2)
+        F.fhe_serve_wait(srv, t1, 300)
+        with pytest.raises(F.FheError) as e:
+            F.fhe_serve_wait(srv, t2, 300)
+        assert e.value.code == F.FHE_ECANCELED
+        assert F.fhe_serve_stats(srv)["pool_bytes_in_use"] == 0
+    finally:
+        srv.close()
