@@ -195,6 +195,46 @@ int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, siz
 int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
                uint32_t cols, uint32_t width, void* stream);
 
+/* Circuit calls replay their level schedule as a captured HIP graph (one
+ * per circuit shape and set of buffers, captured on first use; kernel
+ * launches only).  enable = 0 launches every level directly instead.
+ * While per-phase timing is on (fhe_ctx_set_timing) levels are launched
+ * directly so that each launch can be timed. */
+int fhe_ctx_set_graphs(fhe_ctx* ctx, int enable);
+
+/* ---------------------------------------------------------------------- */
+/* Launch shapes and the autotuner (batching of gates per circuit level).   */
+/* A batch of `width` gates runs with the shape stored for its width bucket */
+/* (bucket b covers widths 2^(b-1) < w <= 2^b, the last bucket, b = 15,     */
+/* every width above 2^14).  Shapes:                                        */
+/*   waves_per_gate = 1, gates_per_group in {1, 2, 4}: one wavefront per    */
+/*     gate, that many ciphertexts per workgroup (throughput shape);        */
+/*   waves_per_gate = 2, gates_per_group = 1: two wavefronts split every    */
+/*     CMux of one gate (latency shape for levels narrower than the chip).  */
+/* The shape changes only the schedule: every shape computes the same      */
+/* words.  Captured level schedules are recaptured after a change.          */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t waves_per_gate;
+    uint32_t gates_per_group;
+} fhe_launch_config;
+
+/* Times every shape on synthetic gate batches of width 1, 2, 4, ... up to
+ * max_width (at most 2^15; reps timed runs each after one warm-up run, the
+ * fastest kept) on the context's device and stores the fastest shape per
+ * bucket; wider buckets take the widest measured one's.  Synchronous:
+ * allocates and frees two batches of max_width samples and waits for the
+ * device.  EINVAL: max_width or reps is 0. */
+int fhe_ctx_autotune(fhe_ctx* ctx, uint32_t max_width, uint32_t reps);
+
+/* The shape a batch of `width` gates (width >= 1) runs with. */
+int fhe_ctx_launch_config(const fhe_ctx* ctx, uint32_t width, fhe_launch_config* out);
+
+/* Stores cfg for every bucket that holds a width in [min_width, max_width].
+ * EINVAL: an empty range or a shape outside the list above. */
+int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_width,
+                              const fhe_launch_config* cfg);
+
 /* Number of gates and of levels of a circuit as the library schedules it
  * (kind 0 = add, 1 = mul, 2 = matvec; rows/cols only for matvec). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfhe_mi355x.so")
+# FHE_LIBRARY may point at another build of the same C ABI (e.g. a variant
+# under comparison); by default the in-tree build is used.
+LIB_PATH = os.environ.get("FHE_LIBRARY") or os.path.join(_HERE, "libfhe_mi355x.so")
 
 FHE_OK, FHE_EINVAL, FHE_ENOMEM, FHE_EDEVICE, FHE_EBUSY, FHE_ECANCELED, FHE_EIO = 0, -1, -2, -3, -4, -5, -6
 AND, NAND, OR, NOR, XOR, XNOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
@@ -32,6 +34,10 @@ class fhe_params(C.Structure):
 
 
 _vp = C.c_void_p
+class fhe_launch_config(C.Structure):
+    _fields_ = [("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32)]
+
+
 _SIGS = {
     "fhe_default_params": (C.c_int, [C.POINTER(fhe_params)]),
     "fhe_keygen": (C.c_int, [C.POINTER(fhe_params), C.c_uint64, C.POINTER(_vp), C.POINTER(_vp)]),
@@ -58,6 +64,10 @@ _SIGS = {
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
     "fhe_ctx_set_timing": (C.c_int, [_vp, C.c_int]),
+    "fhe_ctx_set_graphs": (C.c_int, [_vp, C.c_int]),
+    "fhe_ctx_autotune": (C.c_int, [_vp, C.c_uint32, C.c_uint32]),
+    "fhe_ctx_launch_config": (C.c_int, [_vp, C.c_uint32, C.POINTER(fhe_launch_config)]),
+    "fhe_ctx_set_launch_config": (C.c_int, [_vp, C.c_uint32, C.c_uint32, C.POINTER(fhe_launch_config)]),
     "fhe_ctx_timing": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "fhe_serve_create": (C.c_int, [_vp, C.c_size_t, C.POINTER(_vp)]),
@@ -278,6 +288,31 @@ def fhe_circuit_shape(kind, width, rows=0, cols=0):
 
 def fhe_ctx_set_timing(ctx, enable):
     _check(lib().fhe_ctx_set_timing(ctx.h, 1 if enable else 0), "fhe_ctx_set_timing")
+
+
+def fhe_ctx_set_graphs(ctx, enable):
+    _check(lib().fhe_ctx_set_graphs(ctx.h, 1 if enable else 0), "fhe_ctx_set_graphs")
+
+
+# Launch shapes of the blind-rotation kernel (the autotuner's search space).
+SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1)]
+
+
+def fhe_ctx_autotune(ctx, max_width=4096, reps=2):
+    _check(lib().fhe_ctx_autotune(ctx.h, max_width, reps), "fhe_ctx_autotune")
+
+
+def fhe_ctx_launch_config(ctx, width):
+    """(waves_per_gate, gates_per_group) used for a batch of `width` gates."""
+    c = fhe_launch_config()
+    _check(lib().fhe_ctx_launch_config(ctx.h, width, C.byref(c)), "fhe_ctx_launch_config")
+    return (c.waves_per_gate, c.gates_per_group)
+
+
+def fhe_ctx_set_launch_config(ctx, min_width, max_width, shape):
+    c = fhe_launch_config(*shape)
+    _check(lib().fhe_ctx_set_launch_config(ctx.h, min_width, max_width, C.byref(c)),
+           "fhe_ctx_set_launch_config")
 
 
 def fhe_ctx_timing(ctx):

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfhe_mi355x.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "runtime.cpp", "host_crypto.cpp", "circuits.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "host_crypto.cpp", "circuits.cpp", "serve.cpp", "tuner.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           # no packed-FP32 instructions anywhere in device code
@@ -46,18 +46,22 @@ def _compile(src: str, verbose: bool, resource_usage: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
+def build(verbose: bool = False, resource_usage: bool = False, out: str = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, resource_usage), SOURCES))
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, resource_usage="--resource-usage" in sys.argv))
+    out = None
+    if "-o" in sys.argv:
+        out = os.path.abspath(sys.argv[sys.argv.index("-o") + 1])
+    print(build(verbose="-v" in sys.argv, resource_usage="--resource-usage" in sys.argv, out=out))

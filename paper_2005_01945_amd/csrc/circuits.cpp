@@ -139,9 +139,21 @@ struct Plan {
     uint32_t max_width = 0;
 };
 
+// A level schedule captured as a HIP graph for one set of caller buffers.
+struct CapturedRun {
+    hipGraphExec_t exec = nullptr;
+    uint64_t big_generation = 0;
+    uint64_t tune_generation = 0;
+    uint64_t last_use = 0;
+};
+
 struct CircuitCache {
     std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, size_t>, Plan> plans;
+    std::map<std::tuple<const Plan*, const void*, const void*, const void*>, CapturedRun> graphs;
+    uint64_t clock = 0;
 };
+
+constexpr size_t kMaxGraphs = 64;
 
 namespace {
 
@@ -224,6 +236,41 @@ int get_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, s
     return FHE_OK;
 }
 
+int enqueue_levels(fhe_ctx* ctx, const Plan* P, dev::GateIO io, hipStream_t s) {
+    for (uint32_t L = 0; L < P->levels; ++L) {
+        io.desc = P->desc + P->level_off[L];
+        int rc = run_gate_batch(ctx, io, P->level_width[L], s);
+        if (rc) return rc;
+    }
+    return FHE_OK;
+}
+
+void drop_graph(CapturedRun& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+}
+
+// Captures the level schedule of P over these buffers on the context's own
+// stream (kernel launches only) and instantiates it.
+int capture_levels(fhe_ctx* ctx, const Plan* P, const dev::GateIO& io, CapturedRun* out) {
+    int rc = ctx_reserve_big(ctx, P->max_width);  // no allocation may happen while capturing
+    if (rc) return rc;
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    rc = enqueue_levels(ctx, P, io, ctx->stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->stream, &graph);
+    if (rc == FHE_OK && e != hipSuccess) rc = hip_fail(e, "graph capture");
+    if (rc == FHE_OK) {
+        e = hipGraphInstantiate(&out->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "graph instantiation");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    out->big_generation = ctx->big_generation;
+    out->tune_generation = ctx->tune_generation;
+    return rc;
+}
+
 int run_circuit(fhe_ctx* ctx, int kind, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
                 uint32_t w, uint32_t rows, uint32_t cols, hipStream_t s, const char* name) {
     if (!ctx) return set_error(FHE_EINVAL, "%s: null context", name);
@@ -239,18 +286,43 @@ int run_circuit(fhe_ctx* ctx, int kind, const uint32_t* A, const uint32_t* B, ui
     io.region[kRegionB] = const_cast<uint32_t*>(B);
     io.region[kRegionR] = R;
     io.region[kRegionPool] = P->pool;
-    for (uint32_t L = 0; L < P->levels; ++L) {
-        io.desc = P->desc + P->level_off[L];
-        rc = run_gate_batch(ctx, io, P->level_width[L], s);
-        if (rc) return rc;
+    if (!ctx->use_graphs || ctx->timing) return enqueue_levels(ctx, P, io, s);
+
+    CircuitCache& C = *ctx->circuits;
+    auto key = std::make_tuple((const Plan*)P, (const void*)A, (const void*)B, (const void*)R);
+    CapturedRun& g = C.graphs[key];
+    if (g.exec && (g.big_generation != ctx->big_generation || g.tune_generation != ctx->tune_generation))
+        drop_graph(g);  // scratch moved or launch shapes changed
+    if (!g.exec) {
+        if (C.graphs.size() > kMaxGraphs) {  // evict the least recently used other entry
+            auto victim = C.graphs.end();
+            for (auto it = C.graphs.begin(); it != C.graphs.end(); ++it)
+                if (it->first != key && (victim == C.graphs.end() || it->second.last_use < victim->second.last_use))
+                    victim = it;
+            if (victim != C.graphs.end()) {
+                drop_graph(victim->second);
+                C.graphs.erase(victim);
+            }
+        }
+        CapturedRun& slot = C.graphs[key];
+        rc = capture_levels(ctx, P, io, &slot);
+        if (rc) {
+            drop_graph(slot);
+            C.graphs.erase(key);
+            return rc;
+        }
     }
-    return FHE_OK;
+    CapturedRun& run = C.graphs[key];
+    run.last_use = ++C.clock;
+    hipError_t e = hipGraphLaunch(run.exec, s);
+    return e == hipSuccess ? FHE_OK : hip_fail(e, "graph launch");
 }
 
 }  // namespace
 
 void destroy_circuit_cache(fhe_ctx* ctx) {
     if (!ctx->circuits) return;
+    for (auto& kv : ctx->circuits->graphs) drop_graph(kv.second);
     for (auto& kv : ctx->circuits->plans) free_plan(kv.second);
     delete ctx->circuits;
     ctx->circuits = nullptr;

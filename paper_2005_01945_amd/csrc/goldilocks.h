@@ -20,36 +20,78 @@ constexpr uint64_t P = 0xFFFFFFFF00000001ull;
 constexpr uint64_t EPS = 0xFFFFFFFFull;  // 2^64 mod p
 
 // Every function below takes and returns canonical values (in [0, p)).
-// Carries are read from the top bits (majority of the operands' and the
-// complemented result's sign bits) and folded back with a multiply-add
-// c * (2^32 - 1) + s, which on gfx950 keeps them out of scalar lane masks.
+// A carry (or borrow) is a 3-input boolean function of the top bits of the
+// operands and of the wrapped result; on gfx950 that is one v_bitop3_b32,
+// and an arithmetic shift turns its top bit into a 0 / 0xFFFFFFFF mask that
+// is added back as 0 / EPS.  This keeps carries out of scalar lane masks
+// (and the wait states their reuse costs).
 
 GL_FN uint32_t hi32(uint64_t a) { return (uint32_t)(a >> 32); }
 
-// Carry out of the 64-bit sum s = a + b (mod 2^64), as 0 or 1.
-GL_FN uint32_t carry64(uint64_t a, uint64_t b, uint64_t s) {
-    const uint32_t a1 = hi32(a), b1 = hi32(b), s1 = hi32(s);
-    return ((a1 & b1) | ((a1 | b1) & ~s1)) >> 31;
+// Bitwise 3-input function with truth table `tt`: bit (a<<2 | b<<1 | c).
+template <uint32_t TT>
+GL_FN uint32_t bitop3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+#else
+    uint32_t r = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((TT >> i) & 1u)
+            r |= ((i & 4) ? a : ~a) & ((i & 2) ? b : ~b) & ((i & 1) ? c : ~c);
+    return r;
+#endif
 }
+
+// 0 or 0xFFFFFFFF from the top bit of v.
+GL_FN uint32_t top_mask(uint32_t v) { return (uint32_t)((int32_t)v >> 31); }
+
+// x + (top bit of v) * EPS, for sums that cannot wrap.  On gfx950 this is a
+// single v_mad_u64_u32 (bit * 0xFFFFFFFF + x); written out because the
+// compiler otherwise turns the multiply into a mask and a 64-bit add that
+// needs a zeroed register pair.  The instruction reads only VGPRs and its
+// carry-out goes to a scalar pair nothing reads.
+GL_FN uint64_t add_eps_if(uint64_t x, uint32_t v) {
+    const uint32_t bit = v >> 31;
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, -1, %3" : "=v"(r), "=s"(carry) : "v"(bit), "v"(x));
+    return r;
+#else
+    return x + (uint64_t)bit * EPS;
+#endif
+}
+
+// The 64-bit value p * (top bit of v) mod 2^64 = -(bit * EPS): (bit, -bit).
+GL_FN uint64_t p_if(uint32_t v) {
+    const uint32_t bit = v >> 31;
+    return ((uint64_t)(0u - bit) << 32) | bit;
+}
+
+// carry of s = a + b: (a & b) | ((a | b) & ~s) = majority(a, b, ~s)
+constexpr uint32_t kCarryTT = 0xD4;
+// borrow of d = a - b: (~a & b) | ((~a | b) & d) = majority(~a, b, d)
+constexpr uint32_t kBorrowTT = 0x8E;
+// a & ~b (c ignored)
+constexpr uint32_t kAndNotTT = 0x30;
 
 // x mod p for any 64-bit x: x >= p exactly when x + EPS wraps.
 GL_FN uint64_t canon(uint64_t x) {
     const uint64_t t = x + EPS;
-    return carry64(x, EPS, t) ? t : x;
+    return add_eps_if(x, bitop3<kAndNotTT>(hi32(x), hi32(t), hi32(t)));
 }
 
-// x + y: t = x + (y + EPS) wraps exactly when x + y >= p, and then t is the
-// reduced sum; otherwise the sum is t - EPS.
+// x + y: t = x + (y + EPS) wraps exactly when x + y >= p, and then the
+// reduced sum is x + y + EPS (mod 2^64); otherwise it is x + y.
 GL_FN uint64_t add(uint64_t x, uint64_t y) {
     const uint64_t y2 = y + EPS;  // < 2^64 because y < p
     const uint64_t t = x + y2;
-    return (uint64_t)carry64(x, y2, t) * EPS + (t - EPS);
+    return add_eps_if(x + y, bitop3<kCarryTT>(hi32(x), hi32(y2), hi32(t)));
 }
 
-// x - y: on borrow add p, i.e. subtract EPS modulo 2^64.
+// x - y: on borrow add p = 2^64 - EPS, i.e. (lo + 1, hi + 0xFFFFFFFF).
 GL_FN uint64_t sub(uint64_t x, uint64_t y) {
     const uint64_t d = x - y;
-    return d - (uint64_t)(x < y) * EPS;
+    return d + p_if(bitop3<kBorrowTT>(hi32(x), hi32(y), hi32(d)));
 }
 
 // (hi * 2^64 + lo) mod p for any hi, lo.  hi = hh*2^32 + hl:
@@ -58,11 +100,11 @@ GL_FN uint64_t reduce128(uint64_t hi, uint64_t lo) {
     const uint64_t hh = hi >> 32;
     const uint32_t hl = (uint32_t)hi;
     uint64_t t0 = lo - hh;
-    // borrow iff lo < hh (< 2^32); then lo - hh + 2^64 >= 2^64 - 2^32, no second wrap
-    t0 -= (uint64_t)((~hi32(lo) & hi32(t0)) >> 31) * EPS;
+    // borrow iff lo < hh (< 2^32): then add p; lo - hh + 2^64 >= 2^64 - 2^32, no second wrap
+    t0 += p_if(bitop3<kAndNotTT>(hi32(t0), hi32(lo), hi32(lo)));
     const uint64_t t1 = (uint64_t)hl * EPS;  // <= (2^32 - 1)^2 < p
-    const uint64_t r = t0 + t1;              // a wrap leaves r < t1, + EPS cannot wrap again
-    return canon((uint64_t)carry64(t0, t1, r) * EPS + r);
+    const uint64_t r = t0 + t1;              // a wrap leaves r < t1: + EPS cannot wrap again
+    return canon(add_eps_if(r, bitop3<kCarryTT>(hi32(t0), hi32(t1), hi32(r))));
 }
 
 // 64 x 64 -> 128-bit product from four 32 x 32 -> 64 partial products.
@@ -90,17 +132,18 @@ GL_FN uint64_t mul_pow2(uint64_t x) {
     if constexpr (S == 0) {
         return x;
     } else if constexpr (S < 64) {
-        const uint64_t A = x << S;                                      // (w1:w0)
-        const uint64_t T = (uint64_t)(uint32_t)(x >> (64 - S)) * EPS + A;  // + w2 (2^32 - 1)
-        const uint64_t R = canon((uint64_t)(T < A) * EPS + T);          // one wrap at most
+        const uint64_t A = x << S;                                   // (w1:w0)
+        const uint64_t W = (uint64_t)(uint32_t)(x >> (64 - S)) * EPS;  // w2 (2^32 - 1) < p
+        const uint64_t T = W + A;
+        const uint64_t R = canon(add_eps_if(T, bitop3<kCarryTT>(hi32(W), hi32(A), hi32(T))));
         if constexpr (S <= 32) {
-            return R;                                                   // w3 = w4 = 0
+            return R;                                                // w3 = w4 = 0
         } else {
-            return sub(R, (uint32_t)(x >> (96 - S)));                   // - w3
+            return sub(R, (uint32_t)(x >> (96 - S)));                // - w3
         }
     } else {
-        const uint64_t B = (uint64_t)(uint32_t)(x << (S - 64)) * EPS;   // w2 (2^32 - 1) < p
-        return sub(B, x >> (96 - S));                                   // - (w4:w3), < 2^63
+        const uint64_t B = (uint64_t)(uint32_t)(x << (S - 64)) * EPS;  // w2 (2^32 - 1) < p
+        return sub(B, x >> (96 - S));                                // - (w4:w3), < 2^63
     }
 }
 

@@ -39,9 +39,18 @@ struct DeviceKeys {
 hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* twf,
                              uint32_t n_lwe, hipStream_t s);
 
+// Kernel shape of a blind-rotation launch.  waves_per_gate = 1: one wave
+// bootstraps a gate, gates_per_group in {1, 2, 4} gates share a workgroup
+// (and its twiddle copy in LDS).  waves_per_gate = 2: two waves split each
+// CMux of one gate (one gate per workgroup; gates_per_group is ignored).
+struct LaunchConfig {
+    uint32_t waves_per_gate;
+    uint32_t gates_per_group;
+};
+
 // Gate prologue + blind rotation + sample extraction: writes big[g][N+1].
 hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
-                               uint32_t count, hipStream_t s);
+                               uint32_t count, LaunchConfig cfg, hipStream_t s);
 
 // Key switching big[g] -> the gate's output sample.
 hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,

@@ -219,24 +219,46 @@ struct WaveLds {
     uint32_t tile[2][32 * 32];
 };
 
-// Shared-memory footprint of one block: twiddles plus one WaveLds per wave
-// (80 KB: two blocks fit a CU's 160 KB, i.e. two waves per SIMD).
+// Shared-memory footprint of a block of WPB one-wave gates: twiddles plus one
+// WaveLds per wave (WPB = 4: 80 KB, so two blocks fit a CU's 160 KB, i.e. two
+// waves per SIMD).
+template <int WPB>
 struct BlockLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
-    WaveLds w[kWavesPerBlock];
+    WaveLds w[WPB];
 };
 
-// Pass hp of a CMux step: D = X^ai ACC_hp - ACC_hp, this half's gadget digit
-// of it (half h extracts digit h), its forward NTT, then the multiply-
-// accumulate against BK_i rows (2hp + h) and (2hp + 1 - h), column h.
-// bk_i: BK_i in the kernel layout [hp][q][sel][64 lanes].
-template <int HP>
-__device__ __forceinline__ void cmux_pass(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
+// Shared memory of one gate bootstrapped by two waves (56 KB): wave w runs
+// pass w of every CMux; wave 1 hands its multiply-accumulate result to wave 0
+// through `part`, and wave 0 finishes the step.
+struct PairLds {
+    uint64_t twf[32 * 32];
+    uint64_t twi[32 * 32];
+    uint32_t acc[2][1024];
+    uint32_t tile[2][2][32 * 32];  // [wave][half]
+    uint64_t part[32][64];         // [register q][lane]
+};
+
+// Pass HP of a CMux step: D = X^ai ACC_HP - ACC_HP (a = ACC_HP), this half's
+// gadget digit of it (half h extracts digit h), its forward NTT, then the
+// multiply-accumulate against BK_i rows (2HP + h) and (2HP + 1 - h), column h,
+// added to mac when ACCUM (else stored).  tile: this half's transpose tile;
+// bk_i: BK_i in the kernel layout [hp][q][sel][64 lanes].  PREFETCH issues
+// the 64 key loads before the digit extraction so that their latency hides
+// behind the forward NTT (128 more registers live across it).
+template <int HP, bool ACCUM, bool PREFETCH>
+__device__ __forceinline__ void cmux_pass(const uint32_t* a, uint32_t* tile, int ai,
+                                          const uint64_t* __restrict__ bk_i,
                                           const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
-    const uint32_t* a = W.acc[HP];
+    uint64_t b_pre[PREFETCH ? 64 : 1];
+    if constexpr (PREFETCH) {
+        const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) b_pre[k] = bkp[k * 64];
+    }
     uint64_t x[32];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -253,7 +275,7 @@ __device__ __forceinline__ void cmux_pass(WaveLds& W, int ai, const uint64_t* __
         }
     }
     sched_fence();
-    ntt1024_fwd(x, W.tile[h], twf, t);
+    ntt1024_fwd(x, tile, twf, t);
     const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -261,27 +283,41 @@ __device__ __forceinline__ void cmux_pass(WaveLds& W, int ai, const uint64_t* __
 #pragma unroll
         for (int q = 4 * c; q < 4 * c + 4; ++q) {
             const uint64_t other = partner64(x[q], h);
-            const uint64_t b_own = bkp[(q * 2 + 0) * 64];
-            const uint64_t b_oth = bkp[(q * 2 + 1) * 64];
+            uint64_t b_own, b_oth;
+            if constexpr (PREFETCH) {
+                b_own = b_pre[q * 2 + 0];
+                b_oth = b_pre[q * 2 + 1];
+            } else {
+                b_own = bkp[(q * 2 + 0) * 64];
+                b_oth = bkp[(q * 2 + 1) * 64];
+            }
             const uint64_t v = gl::add(gl::mul(x[q], b_own), gl::mul(other, b_oth));
-            mac[q] = HP == 0 ? v : gl::add(mac[q], v);
+            mac[q] = ACCUM ? gl::add(mac[q], v) : v;
         }
     }
     sched_fence();
+}
+
+// Inverse NTT of the two output columns (half h: column h) and ACC += their
+// lift to Z/2^32.
+__device__ __forceinline__ void cmux_finish(uint32_t (&acc)[2][1024], uint32_t* tile,
+                                            uint64_t (&mac)[32], const uint64_t* twi, int lane) {
+    const int h = lane >> 5, t = lane & 31;
+    ntt1024_inv(mac, tile, twi, t);
+    uint32_t* mine = acc[h];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) mine[t + 32 * q] += gl::lift32(mac[q]);
 }
 
 // One CMux step on this wave's accumulator W.acc:
 //   ACC += BK_i [x] (X^ai ACC - ACC).
 __device__ __forceinline__ void cmux_step(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
                                           const uint64_t* twf, const uint64_t* twi, int lane) {
-    const int h = lane >> 5, t = lane & 31;
+    const int h = lane >> 5;
     uint64_t mac[32];
-    cmux_pass<0>(W, ai, bk_i, twf, lane, mac);
-    cmux_pass<1>(W, ai, bk_i, twf, lane, mac);
-    ntt1024_inv(mac, W.tile[h], twi, t);
-    uint32_t* mine = W.acc[h];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) mine[t + 32 * q] += gl::lift32(mac[q]);
+    cmux_pass<0, false, false>(W.acc[0], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_pass<1, true, false>(W.acc[1], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_finish(W.acc, W.tile[h], mac, twi, lane);
     wave_lds_sync();
 }
 
@@ -324,39 +360,24 @@ __device__ __forceinline__ uint32_t* gate_output(const GateIO& io, uint32_t g) {
     return io.desc ? wire_ptr(io, io.desc[g].w) : io.out + (size_t)g * NW;
 }
 
-__device__ __forceinline__ void load_twiddles(BlockLds& S, const uint64_t* twf, const uint64_t* twi) {
-    for (int k = threadIdx.x; k < 1024; k += kBlockThreads) {
+template <int THREADS, class L>
+__device__ __forceinline__ void load_twiddles(L& S, const uint64_t* twf, const uint64_t* twi) {
+    for (int k = threadIdx.x; k < 1024; k += THREADS) {
         S.twf[k] = twf[k];
         S.twi[k] = twi[k];
     }
     __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Kernels.
-// ---------------------------------------------------------------------------
-
-// Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
-// sample extraction.  One wave per gate, four gates per block.
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_blind_rotate(DeviceKeys K, GateIO io,
-                                                                uint32_t* __restrict__ big,
-                                                                uint32_t count) {
-    __shared__ BlockLds S;
-    load_twiddles(S, K.twf, K.twi);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t g = blockIdx.x * kWavesPerBlock + wave;
-    if (g >= count) return;
-    const int h = lane >> 5, t = lane & 31;
-
-    // Prologue: combined sample, modulus switched to Z_2N.  Lane l keeps
-    // abar of words l + 64k in ab[k].
+// Gate linear combination and modulus switch to Z_2N.  Lane l keeps abar of
+// words l + 64k in ab[k]; returns bbar (uniform).
+__device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int lane, uint32_t (&ab)[8]) {
     uint32_t op;
     const uint32_t *c1, *c2;
     gate_operands(io, g, op, c1, c2);
     uint32_t kappa;
     int32_t s1, s2;
     gate_consts(op, kappa, s1, s2);
-    uint32_t ab[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int w = lane + 64 * k;
@@ -367,21 +388,52 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
         }
         ab[k] = (v + (1u << 20)) >> 21;
     }
-    const int bbar = __builtin_amdgcn_readlane(ab[7], NLWE - 448);
+    return __builtin_amdgcn_readlane(ab[7], NLWE - 448);
+}
 
-    // ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... + X^(N-1)).
-    WaveLds& W = S.w[wave];
-    {
-        const int c = (2 * N - bbar) & (2 * N - 1);
-        const int cm = c & (N - 1);
-        const uint32_t neg = (c >= N) ? 1u : 0u;
+// Test-vector rotation: ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... +
+// X^(N-1)).  Lane l = 32h + t writes coefficients t + 32q of polynomial h.
+__device__ __forceinline__ void acc_init(uint32_t (&acc)[2][1024], int bbar, int h, int t) {
+    const int c = (2 * N - bbar) & (2 * N - 1);
+    const int cm = c & (N - 1);
+    const uint32_t neg = (c >= N) ? 1u : 0u;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const int m = t + 32 * q;
-            const uint32_t sgn = (m >= cm) ? neg : 1u - neg;  // 1 -> -mu
-            W.acc[h][m] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
-        }
+    for (int q = 0; q < 32; ++q) {
+        const int m = t + 32 * q;
+        const uint32_t sgn = (m >= cm) ? neg : 1u - neg;  // 1 -> -mu
+        acc[h][m] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
     }
+}
+
+// Sample extraction of coefficient 0: a'_0 = a_0, a'_m = -a_(N-m), b' = b_0,
+// by THREADS threads with index `tid`.
+template <int THREADS>
+__device__ __forceinline__ void sample_extract(const uint32_t (&acc)[2][1024], uint32_t* o, int tid) {
+    for (int m = tid; m < N; m += THREADS) o[m == 0 ? 0 : N - m] = m == 0 ? acc[0][0] : 0u - acc[0][m];
+    if (tid == 0) o[N] = acc[1][0];
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+// Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
+// sample extraction.  One wave per gate, WPB gates per block; the register
+// budget allows two waves per SIMD.
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_blind_rotate(
+    DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
+    __shared__ BlockLds<WPB> S;
+    load_twiddles<64 * WPB>(S, K.twf, K.twi);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * WPB + wave;
+    if (g >= count) return;
+
+    const int h = lane >> 5, t = lane & 31;
+    uint32_t ab[8];
+    const int bbar = gate_prologue(io, g, lane, ab);
+    WaveLds& W = S.w[wave];
+    acc_init(W.acc, bbar, h, t);
     wave_lds_sync();
 
     // Blind rotation.  abar_i = 0 would give D = 0 and leave ACC unchanged,
@@ -397,11 +449,55 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
             for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
         }
     }
+    sample_extract<64>(W.acc, big + (size_t)g * (N + 1), lane);
+}
 
-    // Sample extraction of coefficient 0: a'_0 = a_0, a'_m = -a_(N-m), b' = b_0.
-    uint32_t* o = big + (size_t)g * (N + 1);
-    for (int m = lane; m < N; m += 64) o[m == 0 ? 0 : N - m] = m == 0 ? W.acc[0][0] : 0u - W.acc[0][m];
-    if (lane == 0) o[N] = W.acc[1][0];
+// The same computation with two waves per gate (one gate per block), for
+// latency: wave w runs pass w of each CMux (digits of ACC_w, their forward
+// NTTs and multiply-accumulate) concurrently; wave 0 then adds wave 1's
+// partial sums, runs the inverse NTTs and updates ACC while wave 1 waits.
+// The critical path of a CMux drops from two passes plus the inverse to one
+// pass plus the inverse; the issued work stays the same.
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_blind_rotate_pair(
+    DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
+    __shared__ PairLds S;
+    load_twiddles<128>(S, K.twf, K.twi);
+    const uint32_t g = blockIdx.x;
+    if (g >= count) return;  // uniform over the block
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, h = lane >> 5, t = lane & 31;
+
+    uint32_t ab[8];
+    const int bbar = gate_prologue(io, g, lane, ab);
+    if (wave == 0) acc_init(S.acc, bbar, h, t);
+    __syncthreads();
+
+    const uint64_t* bk = K.bkd;
+#pragma unroll 1
+    for (int i = 0; i < NLWE; ++i) {
+        const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
+        uint64_t mac[32];
+        if (wave == 0) {
+            cmux_pass<0, false, true>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
+        } else {
+            cmux_pass<1, false, true>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
+#pragma unroll
+            for (int q = 0; q < 32; ++q) S.part[q][lane] = mac[q];
+        }
+        __syncthreads();  // part written; both waves done reading ACC
+        if (wave == 0) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) mac[q] = gl::add(mac[q], S.part[q][lane]);
+            cmux_finish(S.acc, S.tile[0][h], mac, S.twi, lane);
+        }
+        __syncthreads();  // ACC updated; part free
+        bk += 2 * 32 * 2 * 64;
+        if ((i & 63) == 63) {
+#pragma unroll
+            for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+        }
+    }
+    sample_extract<128>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
 }
 
 // Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
@@ -497,10 +593,20 @@ hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* 
 }
 
 hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
-                               uint32_t count, hipStream_t s) {
+                               uint32_t count, LaunchConfig cfg, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_blind_rotate, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
+    if (cfg.waves_per_gate == 2) {
+        hipLaunchKernelGGL(k_blind_rotate_pair, dim3(count), dim3(128), 0, s, K, io, big, count);
+        return hipGetLastError();
+    }
+    const uint32_t wpb = cfg.gates_per_group;
+    const uint32_t blocks = (count + wpb - 1) / wpb;
+    switch (wpb) {
+    case 1: hipLaunchKernelGGL(k_blind_rotate<1>, dim3(blocks), dim3(64), 0, s, K, io, big, count); break;
+    case 2: hipLaunchKernelGGL(k_blind_rotate<2>, dim3(blocks), dim3(128), 0, s, K, io, big, count); break;
+    case 4: hipLaunchKernelGGL(k_blind_rotate<4>, dim3(blocks), dim3(256), 0, s, K, io, big, count); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ int ctx_reserve_big(fhe_ctx* ctx, size_t gates) {
     hipError_t e = hipMalloc((void**)&ctx->big, cap * sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "scratch allocation");
     ctx->big_cap = cap;
+    ctx->big_generation++;
     return FHE_OK;
 }
 
@@ -114,7 +115,8 @@ int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_
             if (!(ev = take_event(ctx))) return set_error(FHE_EDEVICE, "timing event creation failed");
         (void)hipEventRecord(tl.ev[0], s);
     }
-    hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count, s);
+    hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count,
+                                            launch_config_for(ctx, count), s);
     if (e != hipSuccess) return hip_fail(e, "blind rotation launch");
     if (ctx->timing) (void)hipEventRecord(tl.ev[1], s);
     e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)count, s);
@@ -144,6 +146,12 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
     if (!ctx) return set_error(FHE_ENOMEM, "fhe_ctx_create: out of host memory");
     ctx->device = device;
     ctx->P = ck->P;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            ctx->cu_count = prop.multiProcessorCount;
+    }
+    tune_defaults(ctx);
 
     std::vector<uint64_t> twf, twi;
     make_twiddles(twf, twi);
@@ -312,4 +320,10 @@ extern "C" int fhe_ctx_timing(fhe_ctx* ctx, double* br_ms, double* ks_ms, uint64
     if (gates) *gates = g;
     ctx->timed.clear();
     return rc;
+}
+
+extern "C" int fhe_ctx_set_graphs(fhe_ctx* ctx, int enable) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_set_graphs: null context");
+    ctx->use_graphs = enable != 0;
+    return FHE_OK;
 }

@@ -11,6 +11,9 @@
 
 namespace fhe {
 struct CircuitCache;
+// Launch-shape table: bucket b holds the blind-rotation shape of batches of
+// width w with 2^(b-1) < w <= 2^b; the last bucket also holds every wider one.
+constexpr int kTuneBuckets = 16;
 }
 
 struct fhe_ctx {
@@ -24,6 +27,11 @@ struct fhe_ctx {
     uint64_t* twi = nullptr;
     uint32_t* big = nullptr;  // extracted samples of the gates in flight, [gates][N+1]
     size_t big_cap = 0;       // words
+    uint64_t big_generation = 0;  // bumped on every reallocation of big (captured graphs hold it)
+    bool use_graphs = true;       // replay circuit level schedules as captured HIP graphs
+    int cu_count = 256;
+    fhe::dev::LaunchConfig tune[fhe::kTuneBuckets]{};  // launch shape per width bucket
+    uint64_t tune_generation = 0;  // bumped on every change of `tune` (captured graphs hold it)
     fhe::dev::DeviceKeys keys{};
     fhe::CircuitCache* circuits = nullptr;
     // per-phase timing: events {before BR, after BR, after KS} per launch pair
@@ -55,6 +63,10 @@ int check_gfx950(int device);
 uint64_t ntt_psi();
 void make_twiddles(std::vector<uint64_t>& twf, std::vector<uint64_t>& twi);
 int ctx_reserve_big(fhe_ctx* ctx, size_t gates);
+// Launch-shape table (tuner.cpp).
+int tune_bucket(size_t width);
+void tune_defaults(fhe_ctx* ctx);
+dev::LaunchConfig launch_config_for(const fhe_ctx* ctx, size_t width);
 // Enqueues blind rotation + key switching of `count` gates on stream s.
 int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s);
 void destroy_circuit_cache(fhe_ctx* ctx);
