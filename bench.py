@@ -45,17 +45,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(gates_per_launch):
-    """HBM bytes per blind-rotation launch from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def measured_traffic(kernel, gates_per_launch):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none for it or the kernel source changed since the
+    counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash():
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("kernel") != kernel:
         return None
-    return t["bytes_per_gate"] * gates_per_launch
+    return round(t["bytes_per_gate"] * gates_per_launch)
 
 
 def host_threads():
@@ -168,7 +169,9 @@ def main():
     ap.add_argument("--config", default="add16", choices=["add16", "mul32", "matvec"])
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--mul-samples", type=int, default=5)
-    ap.add_argument("--cpu-sample-gates", type=int, default=128)
+    ap.add_argument("--cpu-sample-gates", type=int, default=768)
+    ap.add_argument("--tune-max-width", type=int, default=4096,
+                    help="autotune launch shapes up to this batch width before warmup (0 keeps the defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=300,
                     help="jobs in the serving leg (0 skips it)")
@@ -190,6 +193,14 @@ def main():
     sk, ck = F.fhe_keygen(0)
     ctx = F.Context(ck, 0)
     stream = torch.cuda.current_stream()
+    tuning_s = None
+    if args.tune_max_width > 0:
+        log(f"autotuning launch shapes up to width {args.tune_max_width}")
+        t = time.perf_counter()
+        F.fhe_ctx_autotune(ctx, args.tune_max_width, 1)
+        tuning_s = round(time.perf_counter() - t, 2)
+    shapes = [[1 << b, *F.fhe_ctx_launch_config(ctx, 1 << b)] for b in range(16)]
+    log(f"launch shapes [bucket width, waves/gate, gates/group]: {shapes}")
 
     if args.config == "add16":
         wl = workloads.AddWorkload()
@@ -245,7 +256,10 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     F.fhe_ctx_set_timing(ctx, False)
-    br_ms, ks_ms, launches, timed_gates = F.fhe_ctx_timing(ctx)
+    records = F.fhe_ctx_timing_launches(ctx)
+    br_ms = sum(r["blind_rotate_ms"] for r in records)
+    ks_ms = sum(r["key_switch_ms"] for r in records)
+    launches = len(records)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = gates_per_step / (ms_per_step / 1e3)
     log(f"{ms_per_step:.1f} ms/step, {value:.0f} gates/s; blind rotation {br_ms:.1f} ms, "
@@ -264,15 +278,27 @@ def main():
     if not np.array_equal(got, np.asarray(expect).reshape(-1).astype(np.uint64)):
         raise SystemExit("bench: decrypted results differ from plaintext arithmetic")
 
-    # roofline of the dominant kernel (blind rotation), from the timed region
-    gates_per_launch = timed_gates / max(launches, 1)
-    avg_launch_ms = br_ms / max(launches, 1)
+    # roofline of the dominant kernel (the blind-rotation shape with the most
+    # device time in the timed region), from its launches there
+    by_shape = {}
+    for r in records:
+        e = by_shape.setdefault(r["shape"], {"launches": 0, "gates": 0, "ms": 0.0})
+        e["launches"] += 1
+        e["gates"] += r["gates"]
+        e["ms"] += r["blind_rotate_ms"]
+    shape = max(by_shape, key=lambda k: by_shape[k]["ms"])
+    dom = by_shape[shape]
+    gates_per_launch = dom["gates"] / dom["launches"]
+    avg_launch_ms = dom["ms"] / dom["launches"]
     achieved = LANE_OPS_PER_GATE * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
+    kernel = "k_blind_rotate_pair" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(gates_per_launch),
-                "kernel": "k_blind_rotate", "avg_launch_ms": round(avg_launch_ms, 3),
+                "traffic": measured_traffic(kernel, gates_per_launch),
+                "kernel": kernel, "launches": dom["launches"], "avg_launch_ms": round(avg_launch_ms, 3),
                 "gates_per_launch": round(gates_per_launch, 1)}
+    per_shape = {f"{k[0]}x{k[1]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
+                 for k, v in sorted(by_shape.items())}
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
@@ -346,6 +372,8 @@ def main():
         "config": workload,
         "plain": plain, "mul32_latency": mul, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
+        "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
+                          "timed_by_shape": per_shape},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -222,7 +222,8 @@ typedef struct {
 /* Times every shape on synthetic gate batches of width 1, 2, 4, ... up to
  * max_width (at most 2^15; reps timed runs each after one warm-up run, the
  * fastest kept) on the context's device and stores the fastest shape per
- * bucket; wider buckets take the widest measured one's.  Synchronous:
+ * bucket (the default shape of a bucket stays unless another is more than
+ * 2% faster); wider buckets take the widest measured one's.  Synchronous:
  * allocates and frees two batches of max_width samples and waits for the
  * device.  EINVAL: max_width or reps is 0. */
 int fhe_ctx_autotune(fhe_ctx* ctx, uint32_t max_width, uint32_t reps);
@@ -313,6 +314,18 @@ void fhe_serve_destroy(fhe_server* srv);
 int fhe_ctx_set_timing(fhe_ctx* ctx, int enable);
 int fhe_ctx_timing(fhe_ctx* ctx, double* blind_rotate_ms, double* key_switch_ms,
                    uint64_t* launches, uint64_t* gates);
+
+/* The same records launch by launch, with the shape each ran with.  Waits
+ * for the recorded work; writes min(recorded, max) records in launch order
+ * to out, the number recorded to *count, and resets the records. */
+typedef struct {
+    uint64_t gates;
+    uint32_t waves_per_gate;
+    uint32_t gates_per_group;
+    double blind_rotate_ms;
+    double key_switch_ms;
+} fhe_launch_record;
+int fhe_ctx_timing_launches(fhe_ctx* ctx, fhe_launch_record* out, size_t max, size_t* count);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* fhe_last_error(void);

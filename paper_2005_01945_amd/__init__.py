@@ -38,6 +38,11 @@ class fhe_launch_config(C.Structure):
     _fields_ = [("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32)]
 
 
+class fhe_launch_record(C.Structure):
+    _fields_ = [("gates", C.c_uint64), ("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32),
+                ("blind_rotate_ms", C.c_double), ("key_switch_ms", C.c_double)]
+
+
 _SIGS = {
     "fhe_default_params": (C.c_int, [C.POINTER(fhe_params)]),
     "fhe_keygen": (C.c_int, [C.POINTER(fhe_params), C.c_uint64, C.POINTER(_vp), C.POINTER(_vp)]),
@@ -66,6 +71,7 @@ _SIGS = {
     "fhe_ctx_set_timing": (C.c_int, [_vp, C.c_int]),
     "fhe_ctx_set_graphs": (C.c_int, [_vp, C.c_int]),
     "fhe_ctx_autotune": (C.c_int, [_vp, C.c_uint32, C.c_uint32]),
+    "fhe_ctx_timing_launches": (C.c_int, [_vp, C.POINTER(fhe_launch_record), C.c_size_t, C.POINTER(C.c_size_t)]),
     "fhe_ctx_launch_config": (C.c_int, [_vp, C.c_uint32, C.POINTER(fhe_launch_config)]),
     "fhe_ctx_set_launch_config": (C.c_int, [_vp, C.c_uint32, C.c_uint32, C.POINTER(fhe_launch_config)]),
     "fhe_ctx_timing": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -313,6 +319,18 @@ def fhe_ctx_set_launch_config(ctx, min_width, max_width, shape):
     c = fhe_launch_config(*shape)
     _check(lib().fhe_ctx_set_launch_config(ctx.h, min_width, max_width, C.byref(c)),
            "fhe_ctx_set_launch_config")
+
+
+def fhe_ctx_timing_launches(ctx, max_records=1 << 16):
+    """Per-launch records since the last timing call: list of dicts with
+    gates, shape (waves_per_gate, gates_per_group), blind_rotate_ms,
+    key_switch_ms."""
+    buf = (fhe_launch_record * max_records)()
+    n = C.c_size_t()
+    _check(lib().fhe_ctx_timing_launches(ctx.h, buf, max_records, C.byref(n)), "fhe_ctx_timing_launches")
+    return [{"gates": r.gates, "shape": (r.waves_per_gate, r.gates_per_group),
+             "blind_rotate_ms": r.blind_rotate_ms, "key_switch_ms": r.key_switch_ms}
+            for r in buf[:min(n.value, max_records)]]
 
 
 def fhe_ctx_timing(ctx):

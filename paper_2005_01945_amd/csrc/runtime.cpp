@@ -109,14 +109,14 @@ int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_
     if (count == 0) return FHE_OK;
     int rc = ctx_reserve_big(ctx, count);
     if (rc) return rc;
-    fhe_ctx::TimedLaunch tl{{nullptr, nullptr, nullptr}, count};
+    const dev::LaunchConfig cfg = launch_config_for(ctx, count);
+    fhe_ctx::TimedLaunch tl{{nullptr, nullptr, nullptr}, count, cfg};
     if (ctx->timing) {
         for (auto& ev : tl.ev)
             if (!(ev = take_event(ctx))) return set_error(FHE_EDEVICE, "timing event creation failed");
         (void)hipEventRecord(tl.ev[0], s);
     }
-    hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count,
-                                            launch_config_for(ctx, count), s);
+    hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count, cfg, s);
     if (e != hipSuccess) return hip_fail(e, "blind rotation launch");
     if (ctx->timing) (void)hipEventRecord(tl.ev[1], s);
     e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)count, s);
@@ -296,29 +296,51 @@ extern "C" int fhe_ctx_set_timing(fhe_ctx* ctx, int enable) {
     return FHE_OK;
 }
 
-extern "C" int fhe_ctx_timing(fhe_ctx* ctx, double* br_ms, double* ks_ms, uint64_t* launches,
-                              uint64_t* gates) {
-    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_timing: null context");
+// Waits for every recorded launch pair, hands each one's figures to `sink`
+// and recycles the events.
+template <class Sink>
+static int drain_timed(fhe_ctx* ctx, const char* name, Sink&& sink) {
     DeviceGuard guard(ctx->device);
-    double br = 0, ks = 0;
-    uint64_t g = 0;
     int rc = FHE_OK;
     for (auto& tl : ctx->timed) {
         hipError_t e = hipEventSynchronize(tl.ev[2]);
         float a = 0, b = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&a, tl.ev[0], tl.ev[1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, tl.ev[1], tl.ev[2]);
-        if (e != hipSuccess && rc == FHE_OK) rc = hip_fail(e, "fhe_ctx_timing");
+        if (e != hipSuccess && rc == FHE_OK) rc = hip_fail(e, name);
+        sink(tl, (double)a, (double)b);
+        for (hipEvent_t ev : tl.ev) ctx->event_pool.push_back(ev);
+    }
+    ctx->timed.clear();
+    return rc;
+}
+
+extern "C" int fhe_ctx_timing(fhe_ctx* ctx, double* br_ms, double* ks_ms, uint64_t* launches,
+                              uint64_t* gates) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_timing: null context");
+    double br = 0, ks = 0;
+    uint64_t g = 0, n = 0;
+    int rc = drain_timed(ctx, "fhe_ctx_timing", [&](const fhe_ctx::TimedLaunch& tl, double a, double b) {
         br += a;
         ks += b;
         g += tl.gates;
-        for (hipEvent_t ev : tl.ev) ctx->event_pool.push_back(ev);
-    }
+        ++n;
+    });
     if (br_ms) *br_ms = br;
     if (ks_ms) *ks_ms = ks;
-    if (launches) *launches = ctx->timed.size();
+    if (launches) *launches = n;
     if (gates) *gates = g;
-    ctx->timed.clear();
+    return rc;
+}
+
+extern "C" int fhe_ctx_timing_launches(fhe_ctx* ctx, fhe_launch_record* out, size_t max, size_t* count) {
+    if (!ctx || !count || (max && !out)) return set_error(FHE_EINVAL, "fhe_ctx_timing_launches: null argument");
+    size_t n = 0;
+    int rc = drain_timed(ctx, "fhe_ctx_timing_launches", [&](const fhe_ctx::TimedLaunch& tl, double a, double b) {
+        if (n < max) out[n] = fhe_launch_record{tl.gates, tl.cfg.waves_per_gate, tl.cfg.gates_per_group, a, b};
+        ++n;
+    });
+    *count = n;
     return rc;
 }
 

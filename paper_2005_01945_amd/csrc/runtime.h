@@ -39,6 +39,7 @@ struct fhe_ctx {
     struct TimedLaunch {
         hipEvent_t ev[3];
         uint64_t gates;
+        fhe::dev::LaunchConfig cfg;
     };
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;

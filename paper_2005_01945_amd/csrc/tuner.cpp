@@ -21,6 +21,10 @@ namespace {
 
 constexpr dev::LaunchConfig kShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}};
 
+bool same(const dev::LaunchConfig& a, const dev::LaunchConfig& b) {
+    return a.waves_per_gate == b.waves_per_gate && a.gates_per_group == b.gates_per_group;
+}
+
 bool shape_valid(const fhe_launch_config& c) {
     if (c.waves_per_gate == 1) return c.gates_per_group == 1 || c.gates_per_group == 2 || c.gates_per_group == 4;
     return c.waves_per_gate == 2 && c.gates_per_group == 1;
@@ -37,11 +41,12 @@ int tune_bucket(size_t width) {
 // Before any measurement: the two-wave shape while every gate of the batch
 // fits on the chip at once at one wave per SIMD (two 56 KB workgroups per
 // CU), the four-gate one-wave shape beyond.
+static dev::LaunchConfig default_shape(const fhe_ctx* ctx, size_t width) {
+    return width <= (size_t)2 * ctx->cu_count ? dev::LaunchConfig{2, 1} : dev::LaunchConfig{1, 4};
+}
+
 void tune_defaults(fhe_ctx* ctx) {
-    for (int b = 0; b < kTuneBuckets; ++b) {
-        const size_t width = (size_t)1 << b;
-        ctx->tune[b] = width <= (size_t)2 * ctx->cu_count ? dev::LaunchConfig{2, 1} : dev::LaunchConfig{1, 4};
-    }
+    for (int b = 0; b < kTuneBuckets; ++b) ctx->tune[b] = default_shape(ctx, (size_t)1 << b);
     ctx->tune_generation++;
 }
 
@@ -100,8 +105,17 @@ extern "C" int fhe_ctx_autotune(fhe_ctx* ctx, uint32_t max_width, uint32_t reps)
     dev::LaunchConfig best_cfg[kTuneBuckets];
     for (int b = 0; b <= top && e == hipSuccess; ++b) {
         const uint32_t width = 1u << b;
+        // The default shape is timed first and kept unless another one is
+        // more than 2% faster, so near-ties do not flip from run to run.
+        const dev::LaunchConfig incumbent = default_shape(ctx, width);
+        dev::LaunchConfig order[1 + sizeof(kShapes) / sizeof(kShapes[0])];
+        int n_order = 0;
+        order[n_order++] = incumbent;
+        for (const dev::LaunchConfig& c : kShapes)
+            if (!same(c, incumbent)) order[n_order++] = c;
         float best = 0;
-        for (const dev::LaunchConfig& cfg : kShapes) {
+        for (int k = 0; k < n_order; ++k) {
+            const dev::LaunchConfig& cfg = order[k];
             float fastest = 0;
             for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) {  // run 0 warms up
                 e = hipEventRecord(ev[0], ctx->stream);
@@ -113,7 +127,7 @@ extern "C" int fhe_ctx_autotune(fhe_ctx* ctx, uint32_t max_width, uint32_t reps)
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
                 if (r > 0 && (fastest == 0 || ms < fastest)) fastest = ms;
             }
-            if (e == hipSuccess && (best == 0 || fastest < best)) {
+            if (e == hipSuccess && (best == 0 || fastest < 0.98f * best)) {
                 best = fastest;
                 best_cfg[b] = cfg;
             }

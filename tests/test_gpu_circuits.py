@@ -133,3 +133,23 @@ def test_matvec8_serving_size_decrypts(env):
     F.fhe_matvec(ctx, F.to_device(cm), F.to_device(cx), dy, 8, 8, 8)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(sk.decrypt_uint(F.to_host(dy), 8), (M @ x) % 256)
+
+
+def test_matvec64_full_size_decrypts(env):
+    """The 64x64 16-bit matrix-vector product with entries in [0, 256)
+    (2,952,576 gates in 68 levels, all 4096 products batched per level):
+    every output decrypts to M x mod 2^16 (row sums exceed 2^16, so the
+    wraparound is exercised)."""
+    import torch
+    sk, ctx, K = env
+    wl = workloads.MatvecWorkload()
+    M, x = wl.operands()
+    assert int((M @ x).max()) >= 1 << 16
+    cm = sk.encrypt_uint(M.reshape(-1), wl.width, nonce=0)
+    cx = sk.encrypt_uint(x, wl.width, nonce=1 << 40)
+    dy = torch.empty((wl.rows, wl.width, F.WORDS), dtype=torch.int32, device="cuda")
+    log("matvec 64x64 16-bit (2.95 M gates)")
+    F.fhe_matvec(ctx, F.to_device(cm), F.to_device(cx), dy, wl.rows, wl.cols, wl.width)
+    torch.cuda.synchronize()
+    got = F.to_host(dy)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (M @ x) % (1 << wl.width))
