@@ -200,7 +200,7 @@ def main():
         F.fhe_ctx_autotune(ctx, args.tune_max_width, 1)
         tuning_s = round(time.perf_counter() - t, 2)
     shapes = [[1 << b, *F.fhe_ctx_launch_config(ctx, 1 << b)] for b in range(16)]
-    log(f"launch shapes [bucket width, waves/gate, gates/group]: {shapes}")
+    log(f"launch shapes [bucket width, waves/gate, gates/group, arith]: {shapes}")
 
     if args.config == "add16":
         wl = workloads.AddWorkload()
@@ -291,13 +291,13 @@ def main():
     gates_per_launch = dom["gates"] / dom["launches"]
     avg_launch_ms = dom["ms"] / dom["launches"]
     achieved = LANE_OPS_PER_GATE * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
-    kernel = "k_blind_rotate_pair" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}>"
+    kernel = f"k_blind_rotate_pair<{shape[2]}>" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}, {shape[2]}>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(kernel, gates_per_launch),
                 "kernel": kernel, "launches": dom["launches"], "avg_launch_ms": round(avg_launch_ms, 3),
                 "gates_per_launch": round(gates_per_launch, 1)}
-    per_shape = {f"{k[0]}x{k[1]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
+    per_shape = {f"{k[0]}x{k[1]}/arith{k[2]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
                  for k, v in sorted(by_shape.items())}
 
     if args.copy_calibration_mib > 0:

@@ -210,13 +210,17 @@ int fhe_ctx_set_graphs(fhe_ctx* ctx, int enable);
 /*   waves_per_gate = 1, gates_per_group in {1, 2, 4}: one wavefront per    */
 /*     gate, that many ciphertexts per workgroup (throughput shape);        */
 /*   waves_per_gate = 2, gates_per_group = 1: two wavefronts split every    */
-/*     CMux of one gate (latency shape for levels narrower than the chip).  */
-/* The shape changes only the schedule: every shape computes the same      */
-/* words.  Captured level schedules are recaptured after a change.          */
+/*     CMux of one gate (latency shape for levels narrower than the chip);  */
+/*   times either NTT arithmetic (arith 0 or 1).                            */
+/* The shape changes only the schedule and the exact arithmetic used to     */
+/* reach the result: every shape computes the same words.  Captured level   */
+/* schedules are recaptured after a change.                                 */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     uint32_t waves_per_gate;
     uint32_t gates_per_group;
+    uint32_t arith;  /* 0: NTT over p = 2^64 - 2^32 + 1; 1: NTT modulo two
+                        28-bit primes, recombined by CRT (both exact) */
 } fhe_launch_config;
 
 /* Times every shape on synthetic gate batches of width 1, 2, 4, ... up to
@@ -322,6 +326,8 @@ typedef struct {
     uint64_t gates;
     uint32_t waves_per_gate;
     uint32_t gates_per_group;
+    uint32_t arith;
+    uint32_t reserved;  /* 0 */
     double blind_rotate_ms;
     double key_switch_ms;
 } fhe_launch_record;
@@ -331,10 +337,11 @@ int fhe_ctx_timing_launches(fhe_ctx* ctx, fhe_launch_record* out, size_t max, si
 const char* fhe_last_error(void);
 
 /* Test entry: one CMux step of the blind rotation on explicit HOST data,
- * computed on `device` with the production NTT path:
+ * computed on `device` with the production kernels of NTT arithmetic `arith`
+ * (0: Goldilocks prime, 1: two 28-bit primes and CRT; see fhe_launch_config):
  *   acc[2][N] <- acc + BK_i [x] (X^abar acc - acc),
  * bk_i: uint32 [2l][2][N] (coefficient domain, rows r = 2j + p). */
-int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, uint32_t* acc);
+int fhe_debug_cmux(int device, int arith, const uint32_t* bk_i, int32_t abar, uint32_t* acc);
 
 #ifdef __cplusplus
 }

@@ -35,11 +35,12 @@ class fhe_params(C.Structure):
 
 _vp = C.c_void_p
 class fhe_launch_config(C.Structure):
-    _fields_ = [("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32)]
+    _fields_ = [("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32), ("arith", C.c_uint32)]
 
 
 class fhe_launch_record(C.Structure):
     _fields_ = [("gates", C.c_uint64), ("waves_per_gate", C.c_uint32), ("gates_per_group", C.c_uint32),
+                ("arith", C.c_uint32), ("reserved", C.c_uint32),
                 ("blind_rotate_ms", C.c_double), ("key_switch_ms", C.c_double)]
 
 
@@ -85,7 +86,7 @@ _SIGS = {
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "fhe_serve_destroy": (None, [_vp]),
     "fhe_last_error": (C.c_char_p, []),
-    "fhe_debug_cmux": (C.c_int, [C.c_int, _vp, C.c_int32, _vp]),
+    "fhe_debug_cmux": (C.c_int, [C.c_int, C.c_int, _vp, C.c_int32, _vp]),
 }
 
 _lib = None
@@ -300,8 +301,10 @@ def fhe_ctx_set_graphs(ctx, enable):
     _check(lib().fhe_ctx_set_graphs(ctx.h, 1 if enable else 0), "fhe_ctx_set_graphs")
 
 
-# Launch shapes of the blind-rotation kernel (the autotuner's search space).
-SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1)]
+# Launch shapes of the blind-rotation kernel (the autotuner's search space):
+# (waves_per_gate, gates_per_group, arith), arith 0 = Goldilocks NTT,
+# 1 = two-prime NTT.
+SHAPES = [(w, g, a) for a in (0, 1) for (w, g) in ((1, 1), (1, 2), (1, 4), (2, 1))]
 
 
 def fhe_ctx_autotune(ctx, max_width=4096, reps=2):
@@ -309,10 +312,10 @@ def fhe_ctx_autotune(ctx, max_width=4096, reps=2):
 
 
 def fhe_ctx_launch_config(ctx, width):
-    """(waves_per_gate, gates_per_group) used for a batch of `width` gates."""
+    """(waves_per_gate, gates_per_group, arith) used for a batch of `width` gates."""
     c = fhe_launch_config()
     _check(lib().fhe_ctx_launch_config(ctx.h, width, C.byref(c)), "fhe_ctx_launch_config")
-    return (c.waves_per_gate, c.gates_per_group)
+    return (c.waves_per_gate, c.gates_per_group, c.arith)
 
 
 def fhe_ctx_set_launch_config(ctx, min_width, max_width, shape):
@@ -328,7 +331,7 @@ def fhe_ctx_timing_launches(ctx, max_records=1 << 16):
     buf = (fhe_launch_record * max_records)()
     n = C.c_size_t()
     _check(lib().fhe_ctx_timing_launches(ctx.h, buf, max_records, C.byref(n)), "fhe_ctx_timing_launches")
-    return [{"gates": r.gates, "shape": (r.waves_per_gate, r.gates_per_group),
+    return [{"gates": r.gates, "shape": (r.waves_per_gate, r.gates_per_group, r.arith),
              "blind_rotate_ms": r.blind_rotate_ms, "key_switch_ms": r.key_switch_ms}
             for r in buf[:min(n.value, max_records)]]
 
@@ -397,11 +400,12 @@ def fhe_serve_stats(srv):
     return dict(zip(["jobs_done", "gates_done", "launches", "pool_bytes_in_use", "jobs_waiting"], [x.value for x in v]))
 
 
-def fhe_debug_cmux(bk_i, abar, acc, device=0):
-    """One CMux step on host arrays with the production NTT path (test entry)."""
+def fhe_debug_cmux(bk_i, abar, acc, device=0, arith=0):
+    """One CMux step on host arrays with the production kernels of NTT
+    arithmetic `arith` (test entry)."""
     b, pb = _host(bk_i, np.uint32)
     a = np.ascontiguousarray(acc, np.uint32).copy()
-    _check(lib().fhe_debug_cmux(device, pb, abar, a.ctypes.data), "fhe_debug_cmux")
+    _check(lib().fhe_debug_cmux(device, arith, pb, abar, a.ctypes.data), "fhe_debug_cmux")
     return a
 
 

@@ -33,19 +33,31 @@ struct DeviceKeys {
     const uint32_t* zero_row; // 512 zero words (digit 0 rows)
     const uint64_t* twf;      // forward twiddles [32][32]
     const uint64_t* twi;      // inverse twiddles (with N^-1) [32][32]
+    // Two-prime NTT: BK (prime-0 residue in the low word, prime-1 in the high
+    // word, Montgomery form) [n][hp][q][digit][64 lanes], and twiddle tables
+    // int32 [prime][32][32] (8 KB each, read as 1024 uint64).
+    const uint64_t* bkq;
+    const uint64_t* twfq;
+    const uint64_t* twiq;
 };
 
 // BK (uint32 [n][2l][2][N], device) -> NTT-domain kernel layout.
 hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* twf,
                              uint32_t n_lwe, hipStream_t s);
+// The same for the two-prime NTT (twfq: the two-prime forward table).
+hipError_t launch_bk_prepare_q(const uint32_t* bk, uint64_t* bkq, const uint64_t* twfq,
+                               uint32_t n_lwe, hipStream_t s);
 
 // Kernel shape of a blind-rotation launch.  waves_per_gate = 1: one wave
 // bootstraps a gate, gates_per_group in {1, 2, 4} gates share a workgroup
 // (and its twiddle copy in LDS).  waves_per_gate = 2: two waves split each
 // CMux of one gate (one gate per workgroup; gates_per_group is ignored).
+// arith: 0 = NTT over the Goldilocks prime, 1 = NTT modulo two 28-bit
+// primes recombined by CRT.  Every shape gives the same words.
 struct LaunchConfig {
     uint32_t waves_per_gate;
     uint32_t gates_per_group;
+    uint32_t arith;
 };
 
 // Gate prologue + blind rotation + sample extraction: writes big[g][N+1].
@@ -56,8 +68,9 @@ hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* 
 hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
                              uint32_t count, hipStream_t s);
 
-// One CMux on acc[2][N] (device) with prepared BK_i (bkd of one iteration).
-hipError_t launch_debug_cmux(const DeviceKeys& K, const uint64_t* bkd_i, int32_t abar,
+// One CMux on acc[2][N] (device) with prepared BK_i (one iteration of bkd
+// for arith 0, of bkq for arith 1).
+hipError_t launch_debug_cmux(const DeviceKeys& K, int arith, const uint64_t* bk_i, int32_t abar,
                              uint32_t* acc, hipStream_t s);
 
 }  // namespace dev

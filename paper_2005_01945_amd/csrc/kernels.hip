@@ -28,6 +28,7 @@
 #include "fhe_internal.h"
 #include "goldilocks.h"
 #include "kernels.h"
+#include "modq.h"
 
 namespace fhe {
 namespace dev {
@@ -321,6 +322,231 @@ __device__ __forceinline__ void cmux_step(WaveLds& W, int ai, const uint64_t* __
     wave_lds_sync();
 }
 
+// ---------------------------------------------------------------------------
+// The same CMux with the products computed modulo two 28-bit primes q0, q1
+// (modq.h) and recombined by the Chinese remainder theorem.  Each value of
+// the 64-bit layout holds the prime-0 residue in its low word and the prime-1
+// residue in its high word (signed 32-bit each); BK is in the Montgomery form
+// c R mod q with |c| <= q/2, in the layout [i][hp][q][digit][lane 32c + t].
+// Twiddle tables (LDS, int32): forward [prime][q][t] = psi^(t(2 brv5(q)+1)) R,
+// inverse [prime][r][j] = psi^(-r(2j+1)) N^-1 R.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int32_t lo_of(uint64_t v) { return (int32_t)(uint32_t)v; }
+__device__ __forceinline__ int32_t hi_of(uint64_t v) { return (int32_t)(uint32_t)(v >> 32); }
+__device__ __forceinline__ uint64_t pack2(int32_t a, int32_t b) {
+    return ((uint64_t)(uint32_t)b << 32) | (uint32_t)a;
+}
+
+// 32 x 32 transpose of 32-bit values (same tile and swizzle as transpose32).
+template <class WR, class RD>
+__device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
+#pragma unroll
+    for (int k = 0; k < 32; ++k) tile[wr(k) * 32 + (t ^ wr(k))] = (uint32_t)x[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) x[k] = (int32_t)tile[t * 32 + (rd(k) ^ t)];
+    wave_lds_sync();
+}
+
+// Forward 1024-point negacyclic NTT modulo q_I of this half's polynomial
+// (|x| < q in); lane t, register r then holds frequency t + 32 brv5(r),
+// bounded by 7 q.
+template <int I>
+__device__ __forceinline__ void ntt1024_fwd_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twf, int t) {
+    mq::ntt32<I, mq::kNeg, 1>(x);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int q = 8 * c; q < 8 * c + 8; ++q) x[q] = mq::mul<I>(x[q], twf[q * 32 + t]);
+    }
+    sched_fence();
+    transpose32_w(x, tile, t, [](int q) { return brv5(q); }, [](int r) { return r; });
+    mq::ntt32<I, mq::kCycFwd, 1>(x);
+}
+
+// Inverse, from the forward's layout with |x| < 2q: lane t, register r then
+// holds the residue (|.| < q) of coefficient t + 32 brv5(r).
+template <int I>
+__device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twi, int t) {
+    mq::ntt32<I, mq::kDitInv, 2>(x);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int r = 8 * c; r < 8 * c + 8; ++r) x[r] = mq::mul<I>(x[r], twi[r * 32 + t]);
+    }
+    sched_fence();
+    transpose32_w(x, tile, t, [](int r) { return r; }, [](int j) { return j; });
+    mq::ntt32<I, mq::kCycInv, 1>(x);
+    // negacyclic twist psi^(-32 q) of output q = brv5(r): rho^(-q)
+    mq::static_for<0, 32>([&](auto R_) {
+        constexpr int r = decltype(R_)::value;
+        constexpr int e = (64 - brv5(r)) % 64;
+        if constexpr (r % 8 == 0) sched_fence();
+        x[r] = mq::mul<I>(x[r], mq::sconst<mq::Mod<I>::rho.v[e]>());
+    });
+    sched_fence();
+}
+
+// Pass HP of a CMux step with two-prime products (see cmux_pass): digits of
+// ACC_HP (half h: digit h), their transforms, and the multiply-accumulate of
+// column h.  mac: low word prime 0, high word prime 1, each |.| < q per pass.
+template <int HP, bool ACCUM, bool PREFETCH>
+__device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, int ai,
+                                            const uint64_t* __restrict__ bk_i, const int32_t* twf,
+                                            int lane, uint64_t (&mac)[32]) {
+    const int h = lane >> 5, t = lane & 31;
+    const int shift = 22 - 10 * h;
+    uint64_t b_pre[PREFETCH ? 64 : 1];
+    if constexpr (PREFETCH) {
+        const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) b_pre[k] = bkp[k * 64];
+    }
+    int32_t x0[32], x1[32];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int q = 8 * c; q < 8 * c + 8; ++q) {
+            const int m = t + 32 * q;
+            const int s = (m - ai) & 2047;
+            const uint32_t v = a[s & 1023];
+            const uint32_t rot = (s & 1024) ? 0u - v : v;
+            const uint32_t D = rot - a[m];
+            const int32_t dg = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
+            x0[q] = dg;
+            x1[q] = dg;
+        }
+    }
+    sched_fence();
+    ntt1024_fwd_q<0>(x0, tile, twf, t);
+    ntt1024_fwd_q<1>(x1, tile, twf + 1024, t);
+    const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int q = 4 * c; q < 4 * c + 4; ++q) {
+            // r[0]: the digit-0 transform (half 0's), r[1]: the digit-1 one
+            const auto s0 = __builtin_amdgcn_permlane32_swap((uint32_t)x0[q], (uint32_t)x0[q], false, false);
+            const auto s1 = __builtin_amdgcn_permlane32_swap((uint32_t)x1[q], (uint32_t)x1[q], false, false);
+            uint64_t b0, b1;
+            if constexpr (PREFETCH) {
+                b0 = b_pre[q * 2 + 0];
+                b1 = b_pre[q * 2 + 1];
+            } else {
+                b0 = bkp[(q * 2 + 0) * 64];
+                b1 = bkp[(q * 2 + 1) * 64];
+            }
+            int32_t v0 = mq::mont<0>((int64_t)(int32_t)s0[0] * lo_of(b0) + (int64_t)(int32_t)s0[1] * lo_of(b1));
+            int32_t v1 = mq::mont<1>((int64_t)(int32_t)s1[0] * hi_of(b0) + (int64_t)(int32_t)s1[1] * hi_of(b1));
+            if constexpr (ACCUM) {
+                v0 += lo_of(mac[q]);
+                v1 += hi_of(mac[q]);
+            }
+            mac[q] = pack2(v0, v1);
+        }
+    }
+    sched_fence();
+}
+
+// Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 -> V mod
+// 2^32.  t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t exactly
+// (|v0 + q0 t| < q0 + q0 q1 / 2 and the true V is in range).
+__device__ __forceinline__ uint32_t crt_low32(int32_t v0, int32_t v1) {
+    constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
+    constexpr int32_t c = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
+    int32_t tq = mq::mul<1>(v1 - v0, c);
+    tq += tq < -(q1 / 2) ? q1 : 0;
+    tq -= tq > q1 / 2 ? q1 : 0;
+    return (uint32_t)v0 + (uint32_t)q0 * (uint32_t)tq;
+}
+
+// Inverse NTTs of both columns (half h: column h), CRT, ACC += result.
+__device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t* tile,
+                                              uint64_t (&mac)[32], const int32_t* twi, int lane) {
+    const int h = lane >> 5, t = lane & 31;
+    int32_t x0[32], x1[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        x0[q] = lo_of(mac[q]);
+        x1[q] = hi_of(mac[q]);
+    }
+    ntt1024_inv_q<0>(x0, tile, twi, t);
+    ntt1024_inv_q<1>(x1, tile, twi + 1024, t);
+    uint32_t* mine = acc[h];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int r = 8 * c; r < 8 * c + 8; ++r) mine[t + 32 * brv5(r)] += crt_low32(x0[r], x1[r]);
+    }
+    sched_fence();
+}
+
+__device__ __forceinline__ void cmux_step_q(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
+                                            const int32_t* twf, const int32_t* twi, int lane) {
+    const int h = lane >> 5;
+    uint64_t mac[32];
+    cmux_pass_q<0, false, false>(W.acc[0], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_pass_q<1, true, false>(W.acc[1], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_finish_q(W.acc, W.tile[h], mac, twi, lane);
+    wave_lds_sync();
+}
+
+// Arithmetic selector of the blind-rotation kernels: 0 = Goldilocks NTT,
+// 1 = two-prime NTT.
+template <int A>
+struct Arith;
+
+template <>
+struct Arith<0> {
+    __host__ __device__ static const uint64_t* bk(const DeviceKeys& K) { return K.bkd; }
+    __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twf; }
+    __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twi; }
+    __device__ __forceinline__ static void step(WaveLds& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
+                                const uint64_t* twi, int lane) {
+        cmux_step(W, ai, bk_i, twf, twi, lane);
+    }
+    template <int HP, bool PREFETCH>
+    __device__ __forceinline__ static void pass(const uint32_t* a, uint32_t* tile, int ai, const uint64_t* bk_i,
+                                const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
+        cmux_pass<HP, false, PREFETCH>(a, tile, ai, bk_i, twf, lane, mac);
+    }
+    __device__ __forceinline__ static uint64_t add(uint64_t x, uint64_t y) { return gl::add(x, y); }
+    __device__ __forceinline__ static void finish(uint32_t (&acc)[2][1024], uint32_t* tile, uint64_t (&mac)[32],
+                                  const uint64_t* twi, int lane) {
+        cmux_finish(acc, tile, mac, twi, lane);
+    }
+};
+
+template <>
+struct Arith<1> {
+    __host__ __device__ static const uint64_t* bk(const DeviceKeys& K) { return K.bkq; }
+    __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twfq; }
+    __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twiq; }
+    __device__ __forceinline__ static void step(WaveLds& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
+                                const uint64_t* twi, int lane) {
+        cmux_step_q(W, ai, bk_i, reinterpret_cast<const int32_t*>(twf),
+                    reinterpret_cast<const int32_t*>(twi), lane);
+    }
+    template <int HP, bool PREFETCH>
+    __device__ __forceinline__ static void pass(const uint32_t* a, uint32_t* tile, int ai, const uint64_t* bk_i,
+                                const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
+        cmux_pass_q<HP, false, PREFETCH>(a, tile, ai, bk_i, reinterpret_cast<const int32_t*>(twf), lane, mac);
+    }
+    __device__ __forceinline__ static uint64_t add(uint64_t x, uint64_t y) {
+        return pack2(lo_of(x) + lo_of(y), hi_of(x) + hi_of(y));
+    }
+    __device__ __forceinline__ static void finish(uint32_t (&acc)[2][1024], uint32_t* tile, uint64_t (&mac)[32],
+                                  const uint64_t* twi, int lane) {
+        cmux_finish_q(acc, tile, mac, reinterpret_cast<const int32_t*>(twi), lane);
+    }
+};
+
 // Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding).
 __device__ __forceinline__ void gate_consts(uint32_t op, uint32_t& kappa, int32_t& s1, int32_t& s2) {
     constexpr uint32_t mu = kMu;
@@ -420,11 +646,11 @@ __device__ __forceinline__ void sample_extract(const uint32_t (&acc)[2][1024], u
 // Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
 // sample extraction.  One wave per gate, WPB gates per block; the register
 // budget allows two waves per SIMD.
-template <int WPB>
+template <int WPB, int A>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_blind_rotate(
     DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
     __shared__ BlockLds<WPB> S;
-    load_twiddles<64 * WPB>(S, K.twf, K.twi);
+    load_twiddles<64 * WPB>(S, Arith<A>::twf(K), Arith<A>::twi(K));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x * WPB + wave;
     if (g >= count) return;
@@ -438,11 +664,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     // Blind rotation.  abar_i = 0 would give D = 0 and leave ACC unchanged,
     // so every step runs unconditionally.
-    const uint64_t* bk = K.bkd;
+    const uint64_t* bk = Arith<A>::bk(K);
 #pragma unroll 1
     for (int i = 0; i < NLWE; ++i) {
         const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
-        cmux_step(W, ai, bk, S.twf, S.twi, lane);
+        Arith<A>::step(W, ai, bk, S.twf, S.twi, lane);
         bk += 2 * 32 * 2 * 64;
         if ((i & 63) == 63) {
 #pragma unroll
@@ -458,10 +684,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 // partial sums, runs the inverse NTTs and updates ACC while wave 1 waits.
 // The critical path of a CMux drops from two passes plus the inverse to one
 // pass plus the inverse; the issued work stays the same.
+template <int A>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_blind_rotate_pair(
     DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
     __shared__ PairLds S;
-    load_twiddles<128>(S, K.twf, K.twi);
+    load_twiddles<128>(S, Arith<A>::twf(K), Arith<A>::twi(K));
     const uint32_t g = blockIdx.x;
     if (g >= count) return;  // uniform over the block
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -472,23 +699,23 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (wave == 0) acc_init(S.acc, bbar, h, t);
     __syncthreads();
 
-    const uint64_t* bk = K.bkd;
+    const uint64_t* bk = Arith<A>::bk(K);
 #pragma unroll 1
     for (int i = 0; i < NLWE; ++i) {
         const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
         uint64_t mac[32];
         if (wave == 0) {
-            cmux_pass<0, false, true>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
+            Arith<A>::template pass<0, true>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
         } else {
-            cmux_pass<1, false, true>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
+            Arith<A>::template pass<1, true>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
 #pragma unroll
             for (int q = 0; q < 32; ++q) S.part[q][lane] = mac[q];
         }
         __syncthreads();  // part written; both waves done reading ACC
         if (wave == 0) {
 #pragma unroll
-            for (int q = 0; q < 32; ++q) mac[q] = gl::add(mac[q], S.part[q][lane]);
-            cmux_finish(S.acc, S.tile[0][h], mac, S.twi, lane);
+            for (int q = 0; q < 32; ++q) mac[q] = Arith<A>::add(mac[q], S.part[q][lane]);
+            Arith<A>::finish(S.acc, S.tile[0][h], mac, S.twi, lane);
         }
         __syncthreads();  // ACC updated; part free
         bk += 2 * 32 * 2 * 64;
@@ -565,18 +792,67 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __
     for (int q = 0; q < 32; ++q) dst[(q * 2 + sel) * 64] = gl::canon(x[q]);
 }
 
+// BK -> two-prime NTT domain in the layout cmux_pass_q reads:
+// bkq[i][hp][q][digit][lane 32c + t] for row r = 2hp + digit, column c, each
+// residue in Montgomery form and centred (|.| <= q/2).
+template <int I>
+__device__ __forceinline__ void bk_residue(const uint32_t* __restrict__ bk, uint32_t poly, int t,
+                                           int32_t (&x)[32], uint32_t* tile, const int32_t* twf) {
+    constexpr int64_t Q = mq::Mod<I>::q;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        int64_t v = (int64_t)(int32_t)bk[(size_t)poly * N + t + 32 * k] % Q;  // |v| < q
+        x[k] = (int32_t)v;
+    }
+    ntt1024_fwd_q<I>(x, tile, twf, t);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        int32_t y = mq::mul<I>(x[k], mq::Mod<I>::rform(mq::Mod<I>::R % Q));  // x R, |.| < q
+        y += y < -(int32_t)(Q / 2) ? (int32_t)Q : 0;
+        y -= y > (int32_t)(Q / 2) ? (int32_t)Q : 0;
+        x[k] = y;
+    }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_bk_prepare_q(const uint32_t* __restrict__ bk,
+                                                                uint64_t* __restrict__ bkq,
+                                                                const uint64_t* __restrict__ twfq,
+                                                                uint32_t npolys) {
+    __shared__ int32_t stw[2 * 32 * 32];
+    __shared__ uint32_t tiles[kWavesPerBlock][2][32 * 32];
+    const int32_t* tw = reinterpret_cast<const int32_t*>(twfq);
+    for (int k = threadIdx.x; k < 2048; k += kBlockThreads) stw[k] = tw[k];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int h = lane >> 5, t = lane & 31;
+    const uint32_t base = 2 * (blockIdx.x * kWavesPerBlock + wave);
+    if (base >= npolys) return;
+    const uint32_t poly = base + h;  // npolys is even
+    int32_t x0[32], x1[32];
+    bk_residue<0>(bk, poly, t, x0, &tiles[wave][h][0], stw);
+    bk_residue<1>(bk, poly, t, x1, &tiles[wave][h][0], stw + 1024);
+    const uint32_t i = poly / 8, r = (poly / 2) % 4, c = poly % 2;
+    const uint32_t hp = r >> 1, digit = r & 1;
+    uint64_t* dst = bkq + (size_t)i * (2 * 32 * 2 * 64) + (size_t)hp * (32 * 2 * 64) + 32 * c + t;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) dst[(q * 2 + digit) * 64] = pack2(x0[q], x1[q]);
+}
+
 // One CMux on acc[2][N] in global memory (single wave).
-__global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bkd_i,
+template <int A>
+__global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bk_i,
                                                    int32_t abar, uint32_t* __restrict__ accg) {
     __shared__ uint64_t stw[2][32 * 32];
     __shared__ WaveLds W;
+    const uint64_t* twf = Arith<A>::twf(K);
+    const uint64_t* twi = Arith<A>::twi(K);
     for (int k = threadIdx.x; k < 1024; k += 64) {
-        stw[0][k] = K.twf[k];
-        stw[1][k] = K.twi[k];
+        stw[0][k] = twf[k];
+        stw[1][k] = twi[k];
     }
     for (int k = threadIdx.x; k < 2 * N; k += 64) W.acc[k / N][k % N] = accg[k];
     __syncthreads();
-    cmux_step(W, abar, bkd_i, stw[0], stw[1], threadIdx.x);
+    Arith<A>::step(W, abar, bk_i, stw[0], stw[1], threadIdx.x);
     __syncthreads();
     for (int k = threadIdx.x; k < 2 * N; k += 64) accg[k] = W.acc[k / N][k % N];
 }
@@ -592,22 +868,34 @@ hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
-                               uint32_t count, LaunchConfig cfg, hipStream_t s) {
-    if (count == 0) return hipSuccess;
+template <int A>
+static hipError_t launch_blind_rotate_a(const DeviceKeys& K, const GateIO& io, uint32_t* big,
+                                        uint32_t count, LaunchConfig cfg, hipStream_t s) {
     if (cfg.waves_per_gate == 2) {
-        hipLaunchKernelGGL(k_blind_rotate_pair, dim3(count), dim3(128), 0, s, K, io, big, count);
+        hipLaunchKernelGGL(k_blind_rotate_pair<A>, dim3(count), dim3(128), 0, s, K, io, big, count);
         return hipGetLastError();
     }
     const uint32_t wpb = cfg.gates_per_group;
     const uint32_t blocks = (count + wpb - 1) / wpb;
     switch (wpb) {
-    case 1: hipLaunchKernelGGL(k_blind_rotate<1>, dim3(blocks), dim3(64), 0, s, K, io, big, count); break;
-    case 2: hipLaunchKernelGGL(k_blind_rotate<2>, dim3(blocks), dim3(128), 0, s, K, io, big, count); break;
-    case 4: hipLaunchKernelGGL(k_blind_rotate<4>, dim3(blocks), dim3(256), 0, s, K, io, big, count); break;
+    case 1: hipLaunchKernelGGL((k_blind_rotate<1, A>), dim3(blocks), dim3(64), 0, s, K, io, big, count); break;
+    case 2: hipLaunchKernelGGL((k_blind_rotate<2, A>), dim3(blocks), dim3(128), 0, s, K, io, big, count); break;
+    case 4: hipLaunchKernelGGL((k_blind_rotate<4, A>), dim3(blocks), dim3(256), 0, s, K, io, big, count); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
+                               uint32_t count, LaunchConfig cfg, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    if (cfg.waves_per_gate != 1 && cfg.waves_per_gate != 2) return hipErrorInvalidValue;
+    if (cfg.arith == 1) {
+        if (!K.bkq) return hipErrorInvalidValue;
+        return launch_blind_rotate_a<1>(K, io, big, count, cfg, s);
+    }
+    if (cfg.arith != 0) return hipErrorInvalidValue;
+    return launch_blind_rotate_a<0>(K, io, big, count, cfg, s);
 }
 
 hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
@@ -618,9 +906,21 @@ hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32
     return hipGetLastError();
 }
 
-hipError_t launch_debug_cmux(const DeviceKeys& K, const uint64_t* bkd_i, int32_t abar,
+hipError_t launch_debug_cmux(const DeviceKeys& K, int arith, const uint64_t* bk_i, int32_t abar,
                              uint32_t* acc, hipStream_t s) {
-    hipLaunchKernelGGL(k_debug_cmux, dim3(1), dim3(64), 0, s, K, bkd_i, abar, acc);
+    if (arith == 1)
+        hipLaunchKernelGGL(k_debug_cmux<1>, dim3(1), dim3(64), 0, s, K, bk_i, abar, acc);
+    else
+        hipLaunchKernelGGL(k_debug_cmux<0>, dim3(1), dim3(64), 0, s, K, bk_i, abar, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_bk_prepare_q(const uint32_t* bk, uint64_t* bkq, const uint64_t* twfq,
+                               uint32_t n_lwe, hipStream_t s) {
+    const uint32_t npolys = n_lwe * 8;
+    const uint32_t waves = npolys / 2;
+    const uint32_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_bk_prepare_q, dim3(blocks), dim3(kBlockThreads), 0, s, bk, bkq, twfq, npolys);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include "goldilocks.h"
 #include "kernels.h"
 #include "runtime.h"
+#include "modq.h"
 
 namespace fhe {
 
@@ -48,6 +49,26 @@ void make_twiddles(std::vector<uint64_t>& twf, std::vector<uint64_t>& twi) {
             const uint64_t e = (2048 - (uint64_t)(r * (2 * t + 1)) % 2048) % 2048;
             twi[r * 32 + t] = gl::canon(gl::mul(ninv, gl::pow(psi, e)));
         }
+}
+
+// Two-prime tables, int32 [prime][32][32] in Montgomery form: forward
+// psi^(t(2 brv5(q)+1)) at [q][t], inverse psi^(-r(2j+1)) N^-1 at [r][j].
+template <int I>
+static void make_twiddles_q1(int32_t* twf, int32_t* twi) {
+    using M = mq::Mod<I>;
+    const uint64_t ninv = mq::powmod(kN, M::q - 2, M::q);
+    for (int q = 0; q < 32; ++q)
+        for (int t = 0; t < 32; ++t) {
+            twf[q * 32 + t] = M::rform(M::psi_pow((int64_t)t * (2 * brv5h(q) + 1)));
+            twi[q * 32 + t] = M::rform(M::psi_pow(-(int64_t)q * (2 * t + 1)) * ninv % M::q);
+        }
+}
+
+void make_twiddles_q(std::vector<int32_t>& twf, std::vector<int32_t>& twi) {
+    twf.assign(2048, 0);
+    twi.assign(2048, 0);
+    make_twiddles_q1<0>(twf.data(), twi.data());
+    make_twiddles_q1<1>(twf.data() + 1024, twi.data() + 1024);
 }
 
 DeviceGuard::DeviceGuard(int dev) {
@@ -155,6 +176,8 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
 
     std::vector<uint64_t> twf, twi;
     make_twiddles(twf, twi);
+    std::vector<int32_t> twfq, twiq;
+    make_twiddles_q(twfq, twiq);
     const size_t n = ck->P.n, N = ck->P.N;
     const size_t bk_words = n * 4 * 2 * N;
     const size_t bkd_words = n * 2 * 32 * 2 * 64;
@@ -180,17 +203,25 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
     if ((e = hipMalloc((void**)&ctx->twf, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->twi, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->bkd, bkd_words * 8)) != hipSuccess) return fail(e, "bootstrapping key");
+    if ((e = hipMalloc((void**)&ctx->bkq, bkd_words * 8)) != hipSuccess) return fail(e, "bootstrapping key");
+    if ((e = hipMalloc((void**)&ctx->twfq, 2048 * 4)) != hipSuccess) return fail(e, "twiddles");
+    if ((e = hipMalloc((void**)&ctx->twiq, 2048 * 4)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->ksk, ksk_dev.size() * 4)) != hipSuccess) return fail(e, "key-switching key");
     if ((e = hipMalloc((void**)&ctx->zero_row, kKskRowWords * 4)) != hipSuccess) return fail(e, "zero row");
     if ((e = hipMalloc((void**)&bk_tmp, bk_words * 4)) != hipSuccess) return fail(e, "bootstrapping key staging");
     if ((e = hipMemcpy(ctx->twf, twf.data(), 1024 * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
     if ((e = hipMemcpy(ctx->twi, twi.data(), 1024 * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
+    if ((e = hipMemcpy(ctx->twfq, twfq.data(), 2048 * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
+    if ((e = hipMemcpy(ctx->twiq, twiq.data(), 2048 * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "upload");
     if ((e = hipMemcpy(ctx->ksk, ksk_dev.data(), ksk_dev.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "upload");
     if ((e = hipMemset(ctx->zero_row, 0, kKskRowWords * 4)) != hipSuccess) return fail(e, "upload");
     if ((e = hipMemcpy(bk_tmp, ck->bk.data(), bk_words * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "upload");
     if ((e = dev::launch_bk_prepare(bk_tmp, ctx->bkd, ctx->twf, (uint32_t)n, ctx->stream)) != hipSuccess)
+        return fail(e, "bootstrapping key transform");
+    if ((e = dev::launch_bk_prepare_q(bk_tmp, ctx->bkq, (const uint64_t*)ctx->twfq, (uint32_t)n, ctx->stream)) !=
+        hipSuccess)
         return fail(e, "bootstrapping key transform");
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return fail(e, "bootstrapping key transform");
     (void)hipFree(bk_tmp);
@@ -201,6 +232,9 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
     ctx->keys.zero_row = ctx->zero_row;
     ctx->keys.twf = ctx->twf;
     ctx->keys.twi = ctx->twi;
+    ctx->keys.bkq = ctx->bkq;
+    ctx->keys.twfq = (const uint64_t*)ctx->twfq;
+    ctx->keys.twiq = (const uint64_t*)ctx->twiq;
     *out = ctx;
     return FHE_OK;
 }
@@ -215,7 +249,7 @@ extern "C" void fhe_ctx_destroy(fhe_ctx* ctx) {
             for (hipEvent_t ev : tl.ev) ctx->event_pool.push_back(ev);
         for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
         for (void* p : {(void*)ctx->bkd, (void*)ctx->ksk, (void*)ctx->zero_row, (void*)ctx->twf,
-                        (void*)ctx->twi, (void*)ctx->big})
+                        (void*)ctx->twi, (void*)ctx->big, (void*)ctx->bkq, (void*)ctx->twfq, (void*)ctx->twiq})
             if (p) (void)hipFree(p);
         if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     }
@@ -254,14 +288,23 @@ extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t
     return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_bootstrap_gate_plain");
 }
 
-extern "C" int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, uint32_t* acc) {
-    if (!bk_i || !acc || abar < 0 || abar >= 2 * (int)kN)
+extern "C" int fhe_debug_cmux(int device, int arith, const uint32_t* bk_i, int32_t abar, uint32_t* acc) {
+    if (!bk_i || !acc || abar < 0 || abar >= 2 * (int)kN || (arith != 0 && arith != 1))
         return set_error(FHE_EINVAL, "fhe_debug_cmux: bad argument");
     int rc = check_gfx950(device);
     if (rc) return rc;
     DeviceGuard guard(device);
     std::vector<uint64_t> twf, twi;
-    make_twiddles(twf, twi);
+    if (arith == 0) {
+        make_twiddles(twf, twi);
+    } else {
+        std::vector<int32_t> f, g;
+        make_twiddles_q(f, g);
+        twf.assign(1024, 0);
+        twi.assign(1024, 0);
+        std::memcpy(twf.data(), f.data(), 8192);
+        std::memcpy(twi.data(), g.data(), 8192);
+    }
     uint64_t *d_twf = nullptr, *d_twi = nullptr, *d_bkd = nullptr;
     uint32_t *d_bk = nullptr, *d_acc = nullptr;
     const size_t bk_words = 4 * 2 * kN, bkd_words = 2 * 32 * 2 * 64;
@@ -278,11 +321,18 @@ extern "C" int fhe_debug_cmux(int device, const uint32_t* bk_i, int32_t abar, ui
         step(hipMemcpy(d_bk, bk_i, bk_words * 4, hipMemcpyHostToDevice));
         step(hipMemcpy(d_acc, acc, 2 * kN * 4, hipMemcpyHostToDevice));
     }
-    if (e == hipSuccess) step(dev::launch_bk_prepare(d_bk, d_bkd, d_twf, 1, nullptr));
+    if (e == hipSuccess)
+        step(arith == 0 ? dev::launch_bk_prepare(d_bk, d_bkd, d_twf, 1, nullptr)
+                        : dev::launch_bk_prepare_q(d_bk, d_bkd, d_twf, 1, nullptr));
     dev::DeviceKeys K{};
-    K.twf = d_twf;
-    K.twi = d_twi;
-    if (e == hipSuccess) step(dev::launch_debug_cmux(K, d_bkd, abar, d_acc, nullptr));
+    if (arith == 0) {
+        K.twf = d_twf;
+        K.twi = d_twi;
+    } else {
+        K.twfq = d_twf;
+        K.twiq = d_twi;
+    }
+    if (e == hipSuccess) step(dev::launch_debug_cmux(K, arith, d_bkd, abar, d_acc, nullptr));
     if (e == hipSuccess) step(hipDeviceSynchronize());
     if (e == hipSuccess) step(hipMemcpy(acc, d_acc, 2 * kN * 4, hipMemcpyDeviceToHost));
     for (void* p : {(void*)d_twf, (void*)d_twi, (void*)d_bkd, (void*)d_bk, (void*)d_acc})
@@ -337,7 +387,8 @@ extern "C" int fhe_ctx_timing_launches(fhe_ctx* ctx, fhe_launch_record* out, siz
     if (!ctx || !count || (max && !out)) return set_error(FHE_EINVAL, "fhe_ctx_timing_launches: null argument");
     size_t n = 0;
     int rc = drain_timed(ctx, "fhe_ctx_timing_launches", [&](const fhe_ctx::TimedLaunch& tl, double a, double b) {
-        if (n < max) out[n] = fhe_launch_record{tl.gates, tl.cfg.waves_per_gate, tl.cfg.gates_per_group, a, b};
+        if (n < max)
+            out[n] = fhe_launch_record{tl.gates, tl.cfg.waves_per_gate, tl.cfg.gates_per_group, tl.cfg.arith, 0, a, b};
         ++n;
     });
     *count = n;

@@ -25,6 +25,9 @@ struct fhe_ctx {
     uint32_t* zero_row = nullptr;
     uint64_t* twf = nullptr;
     uint64_t* twi = nullptr;
+    uint64_t* bkq = nullptr;   // BK for the two-prime NTT
+    int32_t* twfq = nullptr;   // two-prime twiddle tables [2][1024]
+    int32_t* twiq = nullptr;
     uint32_t* big = nullptr;  // extracted samples of the gates in flight, [gates][N+1]
     size_t big_cap = 0;       // words
     uint64_t big_generation = 0;  // bumped on every reallocation of big (captured graphs hold it)
@@ -63,6 +66,7 @@ int hip_fail(hipError_t e, const char* what);
 int check_gfx950(int device);
 uint64_t ntt_psi();
 void make_twiddles(std::vector<uint64_t>& twf, std::vector<uint64_t>& twi);
+void make_twiddles_q(std::vector<int32_t>& twf, std::vector<int32_t>& twi);
 int ctx_reserve_big(fhe_ctx* ctx, size_t gates);
 // Launch-shape table (tuner.cpp).
 int tune_bucket(size_t width);

@@ -19,13 +19,15 @@ namespace fhe {
 
 namespace {
 
-constexpr dev::LaunchConfig kShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}};
+constexpr dev::LaunchConfig kShapes[] = {{1, 1, 0}, {1, 2, 0}, {1, 4, 0}, {2, 1, 0},
+                                         {1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {2, 1, 1}};
 
 bool same(const dev::LaunchConfig& a, const dev::LaunchConfig& b) {
-    return a.waves_per_gate == b.waves_per_gate && a.gates_per_group == b.gates_per_group;
+    return a.waves_per_gate == b.waves_per_gate && a.gates_per_group == b.gates_per_group && a.arith == b.arith;
 }
 
 bool shape_valid(const fhe_launch_config& c) {
+    if (c.arith > 1) return false;
     if (c.waves_per_gate == 1) return c.gates_per_group == 1 || c.gates_per_group == 2 || c.gates_per_group == 4;
     return c.waves_per_gate == 2 && c.gates_per_group == 1;
 }
@@ -42,7 +44,7 @@ int tune_bucket(size_t width) {
 // fits on the chip at once at one wave per SIMD (two 56 KB workgroups per
 // CU), the four-gate one-wave shape beyond.
 static dev::LaunchConfig default_shape(const fhe_ctx* ctx, size_t width) {
-    return width <= (size_t)2 * ctx->cu_count ? dev::LaunchConfig{2, 1} : dev::LaunchConfig{1, 4};
+    return width <= (size_t)2 * ctx->cu_count ? dev::LaunchConfig{2, 1, 0} : dev::LaunchConfig{1, 4, 0};
 }
 
 void tune_defaults(fhe_ctx* ctx) {
@@ -64,6 +66,7 @@ extern "C" int fhe_ctx_launch_config(const fhe_ctx* ctx, uint32_t width, fhe_lau
     const dev::LaunchConfig c = launch_config_for(ctx, width);
     out->waves_per_gate = c.waves_per_gate;
     out->gates_per_group = c.gates_per_group;
+    out->arith = c.arith;
     return FHE_OK;
 }
 
@@ -73,10 +76,11 @@ extern "C" int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint3
     if (min_width == 0 || min_width > max_width)
         return set_error(FHE_EINVAL, "fhe_ctx_set_launch_config: empty width range [%u, %u]", min_width, max_width);
     if (!shape_valid(*cfg))
-        return set_error(FHE_EINVAL, "fhe_ctx_set_launch_config: unsupported shape (%u waves per gate, %u gates per group)",
-                         cfg->waves_per_gate, cfg->gates_per_group);
+        return set_error(FHE_EINVAL,
+                         "fhe_ctx_set_launch_config: unsupported shape (%u waves per gate, %u gates per group, arith %u)",
+                         cfg->waves_per_gate, cfg->gates_per_group, cfg->arith);
     for (int b = tune_bucket(min_width); b <= tune_bucket(max_width); ++b)
-        ctx->tune[b] = dev::LaunchConfig{cfg->waves_per_gate, cfg->gates_per_group};
+        ctx->tune[b] = dev::LaunchConfig{cfg->waves_per_gate, cfg->gates_per_group, cfg->arith};
     ctx->tune_generation++;
     return FHE_OK;
 }

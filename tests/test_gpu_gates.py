@@ -36,9 +36,9 @@ def run_batch(ctx, ops, c0, c1):
 
 
 def cmux_case(bk, abar, acc):
-    got = F.fhe_debug_cmux(bk, abar, acc)
     want = oracle.cmux(bk, abar, acc)
-    np.testing.assert_array_equal(got, want)
+    for arith in (0, 1):
+        np.testing.assert_array_equal(F.fhe_debug_cmux(bk, abar, acc, arith=arith), want)
 
 
 def test_cmux_random():

@@ -1,6 +1,7 @@
 """Launch shapes and the autotuner: every blind-rotation shape (one wave per
-gate with 1, 2 or 4 gates per workgroup; two waves per gate) gives the
-oracle's words bit for bit, and the tuner only ever stores such shapes."""
+gate with 1, 2 or 4 gates per workgroup, or two waves per gate; NTT over the
+Goldilocks prime or modulo two 28-bit primes) gives the oracle's words bit
+for bit, and the tuner only ever stores such shapes."""
 import numpy as np
 import pytest
 
@@ -50,12 +51,13 @@ def test_every_shape_bit_exact(env):
             log(f"{n} gates, shape {shape}")
             np.testing.assert_array_equal(run_batch(ctx, ops, c0, c1), want)
     finally:
-        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4))
+        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))
 
 
-def test_two_wave_shape_on_circuit_output(env):
+@pytest.mark.parametrize("shape", [(2, 1, 0), (2, 1, 1), (1, 4, 1)])
+def test_shape_on_circuit_output(env, shape):
     """Gates whose inputs are themselves gate outputs (noisier, key-switched
-    samples), in the two-wave shape, against the oracle."""
+    samples), against the oracle."""
     sk, ctx, K = env
     n = 6
     ops = workloads.gate_ops(73, n)
@@ -64,27 +66,27 @@ def test_two_wave_shape_on_circuit_output(env):
     c1 = sk.encrypt_bits(workloads.bits(77, n), nonce=5_400_000)
     want = K.bootstrap(ops, c0, c1, threads=8)
     try:
-        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (2, 1))
-        log(f"{n} gates on gate outputs, two waves per gate")
+        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, shape)
+        log(f"{n} gates on gate outputs, shape {shape}")
         np.testing.assert_array_equal(run_batch(ctx, ops, c0, c1), want)
     finally:
-        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4))
+        F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))
 
 
 def test_shape_ranges_and_errors(env):
     _, ctx, _ = env
-    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4))
-    F.fhe_ctx_set_launch_config(ctx, 1, 8, (2, 1))
+    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))
+    F.fhe_ctx_set_launch_config(ctx, 1, 8, (2, 1, 1))
     assert [F.fhe_ctx_launch_config(ctx, w) for w in (1, 5, 8, 9, 1 << 20)] == \
-        [(2, 1), (2, 1), (2, 1), (1, 4), (1, 4)]
-    for bad in [(1, 3), (2, 2), (3, 1), (0, 1)]:
+        [(2, 1, 1), (2, 1, 1), (2, 1, 1), (1, 4, 0), (1, 4, 0)]
+    for bad in [(1, 3, 0), (2, 2, 0), (3, 1, 0), (0, 1, 0), (1, 4, 2)]:
         with pytest.raises(F.FheError):
             F.fhe_ctx_set_launch_config(ctx, 1, 4, bad)
     with pytest.raises(F.FheError):
-        F.fhe_ctx_set_launch_config(ctx, 5, 4, (1, 1))
+        F.fhe_ctx_set_launch_config(ctx, 5, 4, (1, 1, 0))
     with pytest.raises(F.FheError):
         F.fhe_ctx_launch_config(ctx, 0)
-    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4))
+    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))
 
 
 def test_autotune_then_circuit(env):
@@ -114,4 +116,4 @@ def test_autotune_then_circuit(env):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(F.to_host(after), F.to_host(before))
     np.testing.assert_array_equal(sk.decrypt_uint(F.to_host(after), w), (a + b) % (1 << w))
-    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4))
+    F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))

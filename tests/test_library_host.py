@@ -111,7 +111,8 @@ def test_argument_errors():
     assert L.fhe_bootstrap_gate_batch(None, None, None, None, None, 4, None) == F.FHE_EINVAL
     assert L.fhe_add(None, None, None, None, 1, 8, None) == F.FHE_EINVAL
     assert b"null context" in L.fhe_last_error()
-    assert L.fhe_debug_cmux(0, None, 0, None) == F.FHE_EINVAL
+    assert L.fhe_debug_cmux(0, 0, None, 0, None) == F.FHE_EINVAL
+    assert L.fhe_debug_cmux(0, 2, None, 0, None) == F.FHE_EINVAL
 
 
 def test_circuit_shapes_match_oracle_gate_counts():
