@@ -20,17 +20,25 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one gate bootstrap (radix-2 NTT cost model of the method:
-# 500 CMux x (6 NTT-1024 of 5,120 butterflies + 8 x 1,024 pointwise MACs)),
-# in 32-bit integer lane operations: 26 per Goldilocks modmul (four 32x32->64
-# multiplies at quarter rate + reduction), 4 per modular add/sub.
-MODMUL_PER_GATE = 500 * (6 * 5120 + 8 * 1024)
-MODADD_PER_GATE = 500 * (6 * 5120 * 2 + 8 * 1024)
-LANE_OPS_PER_GATE = 26 * MODMUL_PER_GATE + 4 * MODADD_PER_GATE
+# Algorithmic work of one gate bootstrap, in 32-bit integer lane operations,
+# for the radix-2 NTT form of the method: 500 CMux x (6 NTT-1024 of 5,120
+# butterflies + 8 x 1,024 pointwise products + their sums).
+#   arith 0 (NTT over p = 2^64 - 2^32 + 1): 26 lane-ops per modmul (four
+#     32x32->64 products and the reduction), 4 per modular add/sub.
+#   arith 1 (NTT modulo two 28-bit primes): per prime, 3 per Montgomery
+#     modmul and 1 per add/sub; plus the CRT recombination of the 2 x 1,024
+#     output coefficients (7 each).
+MODMUL_PER_CMUX = 6 * 5120 + 8 * 1024
+MODADD_PER_CMUX = 6 * 5120 * 2 + 8 * 1024
+LANE_OPS_PER_GATE = {
+    0: 500 * (26 * MODMUL_PER_CMUX + 4 * MODADD_PER_CMUX),
+    1: 500 * (2 * (3 * MODMUL_PER_CMUX + MODADD_PER_CMUX) + 7 * 2 * 1024),
+}
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blind_rotate_traffic.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2005_01945_amd", "csrc", f) for f in ("kernels.hip", "goldilocks.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2005_01945_amd", "csrc", f)
+               for f in ("kernels.hip", "goldilocks.h", "modq.h")]
 
 
 def log(msg):
@@ -290,7 +298,9 @@ def main():
     dom = by_shape[shape]
     gates_per_launch = dom["gates"] / dom["launches"]
     avg_launch_ms = dom["ms"] / dom["launches"]
-    achieved = LANE_OPS_PER_GATE * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
+    achieved = LANE_OPS_PER_GATE[shape[2]] * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
+    dtype = ("u32 (Torus32) / i32 residues mod two 28-bit primes (NTT)" if shape[2] == 1
+             else "u32 (Torus32) / u64 (NTT mod 2^64-2^32+1)")
     kernel = f"k_blind_rotate_pair<{shape[2]}>" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}, {shape[2]}>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
@@ -368,7 +378,7 @@ def main():
         "value": round(value, 1), "unit": "gates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "graph_ms_per_step": round(graph_ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32 (Torus32) / u64 (Z_p NTT)", "data": "synthetic",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": workload,
         "plain": plain, "mul32_latency": mul, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},

@@ -40,11 +40,11 @@ int tune_bucket(size_t width) {
     return b;
 }
 
-// Before any measurement: the two-wave shape while every gate of the batch
-// fits on the chip at once at one wave per SIMD (two 56 KB workgroups per
-// CU), the four-gate one-wave shape beyond.
+// Before any measurement (defaults from measurements on MI355X): two-prime
+// arithmetic everywhere; the two-wave shape up to two rounds of two 56 KB
+// workgroups per CU, the four-gate one-wave shape beyond.
 static dev::LaunchConfig default_shape(const fhe_ctx* ctx, size_t width) {
-    return width <= (size_t)2 * ctx->cu_count ? dev::LaunchConfig{2, 1, 0} : dev::LaunchConfig{1, 4, 0};
+    return width <= (size_t)4 * ctx->cu_count ? dev::LaunchConfig{2, 1, 1} : dev::LaunchConfig{1, 4, 1};
 }
 
 void tune_defaults(fhe_ctx* ctx) {
