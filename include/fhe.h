@@ -207,7 +207,7 @@ int fhe_ctx_set_graphs(fhe_ctx* ctx, int enable);
 /* A batch of `width` gates runs with the shape stored for its width bucket */
 /* (bucket b covers widths 2^(b-1) < w <= 2^b, the last bucket, b = 15,     */
 /* every width above 2^14).  Shapes:                                        */
-/*   waves_per_gate = 1, gates_per_group in {1, 2, 4}: one wavefront per    */
+/*   waves_per_gate = 1, gates_per_group in {1, 2, 4, 8}: one wavefront per */
 /*     gate, that many ciphertexts per workgroup (throughput shape);        */
 /*   waves_per_gate = 2, gates_per_group = 1: two wavefronts split every    */
 /*     CMux of one gate (latency shape for levels narrower than the chip);  */

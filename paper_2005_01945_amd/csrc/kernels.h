@@ -33,9 +33,9 @@ struct DeviceKeys {
     const uint32_t* zero_row; // 512 zero words (digit 0 rows)
     const uint64_t* twf;      // forward twiddles [32][32]
     const uint64_t* twi;      // inverse twiddles (with N^-1) [32][32]
-    // Two-prime NTT: BK (prime-0 residue in the low word, prime-1 in the high
-    // word, Montgomery form) [n][hp][q][digit][64 lanes], and twiddle tables
-    // int32 [prime][32][32] (8 KB each, read as 1024 uint64).
+    // Two-prime NTT: BK residues (Montgomery form, 32-bit words)
+    // [n][hp][prime][q][digit][64 lanes], and twiddle tables int32
+    // [prime][32][32] (8 KB each, read as 1024 uint64).
     const uint64_t* bkq;
     const uint64_t* twfq;
     const uint64_t* twiq;
@@ -49,7 +49,7 @@ hipError_t launch_bk_prepare_q(const uint32_t* bk, uint64_t* bkq, const uint64_t
                                uint32_t n_lwe, hipStream_t s);
 
 // Kernel shape of a blind-rotation launch.  waves_per_gate = 1: one wave
-// bootstraps a gate, gates_per_group in {1, 2, 4} gates share a workgroup
+// bootstraps a gate, gates_per_group in {1, 2, 4, 8} gates share a workgroup
 // (and its twiddle copy in LDS).  waves_per_gate = 2: two waves split each
 // CMux of one gate (one gate per workgroup; gates_per_group is ignored).
 // arith: 0 = NTT over the Goldilocks prime, 1 = NTT modulo two 28-bit

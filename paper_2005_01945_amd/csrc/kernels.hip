@@ -214,31 +214,40 @@ __device__ __forceinline__ uint64_t partner64(uint64_t v, int h) {
 }
 
 // Per-wave LDS: the accumulator (two polynomials of 1024 words) and one
-// 32 x 32 transpose tile of 32-bit words per half.  16 KB.
-struct WaveLds {
+// 32 x 32 transpose tile of 32-bit words per half (TW words: 32 x 32 with an
+// XOR swizzle for the Goldilocks path, 32 x 33 padded rows for the two-prime
+// path).  16 KB (16.5 KB).
+template <int TW>
+struct WaveLdsT {
     uint32_t acc[2][1024];
-    uint32_t tile[2][32 * 32];
+    uint32_t tile[2][TW];
 };
+using WaveLds = WaveLdsT<32 * 32>;
+
+template <int A>
+constexpr int kTileWords = A == 1 ? 32 * 33 : 32 * 32;
 
 // Shared-memory footprint of a block of WPB one-wave gates: twiddles plus one
-// WaveLds per wave (WPB = 4: 80 KB, so two blocks fit a CU's 160 KB, i.e. two
-// waves per SIMD).
-template <int WPB>
+// per-wave area per wave (WPB = 4 with the Goldilocks path: 80 KB, so two
+// blocks fit a CU's 160 KB, i.e. two waves per SIMD; WPB = 8 with the
+// two-prime path: 146 KB, one block of two waves per SIMD).
+template <int WPB, int A>
 struct BlockLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
-    WaveLds w[WPB];
+    WaveLdsT<kTileWords<A>> w[WPB];
 };
 
 // Shared memory of one gate bootstrapped by two waves (56 KB): wave w runs
 // pass w of every CMux; wave 1 hands its multiply-accumulate result to wave 0
 // through `part`, and wave 0 finishes the step.
+template <int A>
 struct PairLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
     uint32_t acc[2][1024];
-    uint32_t tile[2][2][32 * 32];  // [wave][half]
-    uint64_t part[32][64];         // [register q][lane]
+    uint32_t tile[2][2][kTileWords<A>];  // [wave][half]
+    uint64_t part[32][64];               // [register q][lane]
 };
 
 // Pass HP of a CMux step: D = X^ai ACC_HP - ACC_HP (a = ACC_HP), this half's
@@ -324,10 +333,11 @@ __device__ __forceinline__ void cmux_step(WaveLds& W, int ai, const uint64_t* __
 
 // ---------------------------------------------------------------------------
 // The same CMux with the products computed modulo two 28-bit primes q0, q1
-// (modq.h) and recombined by the Chinese remainder theorem.  Each value of
-// the 64-bit layout holds the prime-0 residue in its low word and the prime-1
-// residue in its high word (signed 32-bit each); BK is in the Montgomery form
-// c R mod q with |c| <= q/2, in the layout [i][hp][q][digit][lane 32c + t].
+// (modq.h) and recombined by the Chinese remainder theorem.  A 64-bit
+// multiply-accumulate value holds the prime-0 residue in its low word and the
+// prime-1 residue in its high word (signed 32-bit each); BK is in the
+// Montgomery form c R mod q with |c| <= q/2, in the 32-bit layout
+// [i][hp][prime][q][digit][lane 32c + t].
 // Twiddle tables (LDS, int32): forward [prime][q][t] = psi^(t(2 brv5(q)+1)) R,
 // inverse [prime][r][j] = psi^(-r(2j+1)) N^-1 R.
 // ---------------------------------------------------------------------------
@@ -338,14 +348,18 @@ __device__ __forceinline__ uint64_t pack2(int32_t a, int32_t b) {
     return ((uint64_t)(uint32_t)b << 32) | (uint32_t)a;
 }
 
-// 32 x 32 transpose of 32-bit values (same tile and swizzle as transpose32).
+// 32 x 32 transpose of 32-bit values through a tile of 32 rows of 33 words:
+// element (row, col) at row*33 + col.  Row writes and column reads are both
+// free of bank conflicts, and every address is a per-lane base (t or 33 t)
+// plus a constant, so no per-register address is kept live.  Before: register
+// k holds (row wr(k), col t); after: register k holds (row t, col rd(k)).
 template <class WR, class RD>
 __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
 #pragma unroll
-    for (int k = 0; k < 32; ++k) tile[wr(k) * 32 + (t ^ wr(k))] = (uint32_t)x[k];
+    for (int k = 0; k < 32; ++k) tile[wr(k) * 33 + t] = (uint32_t)x[k];
     wave_lds_sync();
 #pragma unroll
-    for (int k = 0; k < 32; ++k) x[k] = (int32_t)tile[t * 32 + (rd(k) ^ t)];
+    for (int k = 0; k < 32; ++k) x[k] = (int32_t)tile[t * 33 + rd(k)];
     wave_lds_sync();
 }
 
@@ -390,22 +404,65 @@ __device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, 
     sched_fence();
 }
 
+// Multiply-accumulate of prime I for pass HP: column h of the products of the
+// two digit transforms (r0: digit 0, half 0's; r1: digit 1, half 1's, both
+// obtained with one v_permlane32_swap) with BK rows 2HP and 2HP + 1.
+// bk: the prime-I plane of BK_i for pass HP, [q][digit][64 lanes] words.
+// Key loads run two chunks of four registers ahead of their use; the first
+// two chunks (`pre`) were issued before the forward transform.
+template <int I, bool ACCUM>
+__device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __restrict__ bk,
+                                      uint32_t (&pre)[2][8], int lane, int32_t (&mac)[32]) {
+    uint32_t win[3][8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        win[0][k] = pre[0][k];
+        win[1][k] = pre[1][k];
+    }
+    mq::static_for<0, 8>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
+        if constexpr (c + 2 < 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) win[(c + 2) % 3][k] = bk[((c + 2) * 8 + k) * 64 + lane];
+        }
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = 4 * c + j;
+            const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)x[q], (uint32_t)x[q], false, false);
+            const int32_t b0 = (int32_t)win[c % 3][2 * j], b1 = (int32_t)win[c % 3][2 * j + 1];
+            const int32_t v = mq::mont<I>((int64_t)(int32_t)sw[0] * b0 + (int64_t)(int32_t)sw[1] * b1);
+            mac[q] = ACCUM ? mac[q] + v : v;
+        }
+    });
+    sched_fence();
+}
+
+template <int I>
+__device__ __forceinline__ void prefetch_q(const uint32_t* __restrict__ bk, int lane, uint32_t (&pre)[2][8]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pre[c][k] = bk[(c * 8 + k) * 64 + lane];
+}
+
 // Pass HP of a CMux step with two-prime products (see cmux_pass): digits of
-// ACC_HP (half h: digit h), their transforms, and the multiply-accumulate of
-// column h.  mac: low word prime 0, high word prime 1, each |.| < q per pass.
+// ACC_HP (half h: digit h), then for each prime in turn its transform and
+// multiply-accumulate of column h.  The digits wait for the second prime
+// packed two to a register.  mac: low word prime 0, high word prime 1, each
+// |.| < q per pass.  bk_i: BK_i, [hp][prime][q][digit][64 lanes] words.
 template <int HP, bool ACCUM, bool PREFETCH>
 __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, int ai,
                                             const uint64_t* __restrict__ bk_i, const int32_t* twf,
                                             int lane, uint64_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
-    uint64_t b_pre[PREFETCH ? 64 : 1];
-    if constexpr (PREFETCH) {
-        const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
-#pragma unroll
-        for (int k = 0; k < 64; ++k) b_pre[k] = bkp[k * 64];
-    }
-    int32_t x0[32], x1[32];
+    const uint32_t* bk0 = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192;
+    const uint32_t* bk1 = bk0 + 4096;
+    uint32_t pre[2][8];
+    prefetch_q<0>(bk0, lane, pre);
+    int32_t x[32];
+    uint32_t dp[16];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         sched_fence();
@@ -416,41 +473,34 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
             const uint32_t v = a[s & 1023];
             const uint32_t rot = (s & 1024) ? 0u - v : v;
             const uint32_t D = rot - a[m];
-            const int32_t dg = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
-            x0[q] = dg;
-            x1[q] = dg;
+            x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
         }
+#pragma unroll
+        for (int j = 4 * c; j < 4 * c + 4; ++j)
+            dp[j] = ((uint32_t)x[2 * j] & 0xFFFFu) | ((uint32_t)x[2 * j + 1] << 16);
     }
     sched_fence();
-    ntt1024_fwd_q<0>(x0, tile, twf, t);
-    ntt1024_fwd_q<1>(x1, tile, twf + 1024, t);
-    const uint64_t* bkp = bk_i + (size_t)HP * (32 * 2 * 64) + lane;
+    int32_t m0[32], m1[32];
+    if constexpr (ACCUM) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        sched_fence();
-#pragma unroll
-        for (int q = 4 * c; q < 4 * c + 4; ++q) {
-            // r[0]: the digit-0 transform (half 0's), r[1]: the digit-1 one
-            const auto s0 = __builtin_amdgcn_permlane32_swap((uint32_t)x0[q], (uint32_t)x0[q], false, false);
-            const auto s1 = __builtin_amdgcn_permlane32_swap((uint32_t)x1[q], (uint32_t)x1[q], false, false);
-            uint64_t b0, b1;
-            if constexpr (PREFETCH) {
-                b0 = b_pre[q * 2 + 0];
-                b1 = b_pre[q * 2 + 1];
-            } else {
-                b0 = bkp[(q * 2 + 0) * 64];
-                b1 = bkp[(q * 2 + 1) * 64];
-            }
-            int32_t v0 = mq::mont<0>((int64_t)(int32_t)s0[0] * lo_of(b0) + (int64_t)(int32_t)s0[1] * lo_of(b1));
-            int32_t v1 = mq::mont<1>((int64_t)(int32_t)s1[0] * hi_of(b0) + (int64_t)(int32_t)s1[1] * hi_of(b1));
-            if constexpr (ACCUM) {
-                v0 += lo_of(mac[q]);
-                v1 += hi_of(mac[q]);
-            }
-            mac[q] = pack2(v0, v1);
+        for (int q = 0; q < 32; ++q) {
+            m0[q] = lo_of(mac[q]);
+            m1[q] = hi_of(mac[q]);
         }
     }
-    sched_fence();
+    ntt1024_fwd_q<0>(x, tile, twf, t);
+    mac_q<0, ACCUM>(x, bk0, pre, lane, m0);
+    prefetch_q<1>(bk1, lane, pre);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        x[2 * j] = (int32_t)(dp[j] << 16) >> 16;
+        x[2 * j + 1] = (int32_t)dp[j] >> 16;
+    }
+    ntt1024_fwd_q<1>(x, tile, twf + 1024, t);
+    mac_q<1, ACCUM>(x, bk1, pre, lane, m1);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) mac[q] = pack2(m0[q], m1[q]);
+    (void)PREFETCH;
 }
 
 // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 -> V mod
@@ -487,7 +537,7 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
     sched_fence();
 }
 
-__device__ __forceinline__ void cmux_step_q(WaveLds& W, int ai, const uint64_t* __restrict__ bk_i,
+__device__ __forceinline__ void cmux_step_q(WaveLdsT<32 * 33>& W, int ai, const uint64_t* __restrict__ bk_i,
                                             const int32_t* twf, const int32_t* twi, int lane) {
     const int h = lane >> 5;
     uint64_t mac[32];
@@ -528,7 +578,7 @@ struct Arith<1> {
     __host__ __device__ static const uint64_t* bk(const DeviceKeys& K) { return K.bkq; }
     __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twfq; }
     __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twiq; }
-    __device__ __forceinline__ static void step(WaveLds& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
+    __device__ __forceinline__ static void step(WaveLdsT<32 * 33>& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
                                 const uint64_t* twi, int lane) {
         cmux_step_q(W, ai, bk_i, reinterpret_cast<const int32_t*>(twf),
                     reinterpret_cast<const int32_t*>(twi), lane);
@@ -649,7 +699,7 @@ __device__ __forceinline__ void sample_extract(const uint32_t (&acc)[2][1024], u
 template <int WPB, int A>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_blind_rotate(
     DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
-    __shared__ BlockLds<WPB> S;
+    __shared__ BlockLds<WPB, A> S;
     load_twiddles<64 * WPB>(S, Arith<A>::twf(K), Arith<A>::twi(K));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x * WPB + wave;
@@ -658,7 +708,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int h = lane >> 5, t = lane & 31;
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    WaveLds& W = S.w[wave];
+    auto& W = S.w[wave];
     acc_init(W.acc, bbar, h, t);
     wave_lds_sync();
 
@@ -687,7 +737,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <int A>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_blind_rotate_pair(
     DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
-    __shared__ PairLds S;
+    __shared__ PairLds<A> S;
     load_twiddles<128>(S, Arith<A>::twf(K), Arith<A>::twi(K));
     const uint32_t g = blockIdx.x;
     if (g >= count) return;  // uniform over the block
@@ -793,8 +843,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __
 }
 
 // BK -> two-prime NTT domain in the layout cmux_pass_q reads:
-// bkq[i][hp][q][digit][lane 32c + t] for row r = 2hp + digit, column c, each
-// residue in Montgomery form and centred (|.| <= q/2).
+// bkq[i][hp][prime][q][digit][lane 32c + t] (32-bit words) for row
+// r = 2hp + digit, column c, each residue in Montgomery form and centred
+// (|.| <= q/2).
 template <int I>
 __device__ __forceinline__ void bk_residue(const uint32_t* __restrict__ bk, uint32_t poly, int t,
                                            int32_t (&x)[32], uint32_t* tile, const int32_t* twf) {
@@ -819,7 +870,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare_q(const uint32_t* 
                                                                 const uint64_t* __restrict__ twfq,
                                                                 uint32_t npolys) {
     __shared__ int32_t stw[2 * 32 * 32];
-    __shared__ uint32_t tiles[kWavesPerBlock][2][32 * 32];
+    __shared__ uint32_t tiles[kWavesPerBlock][2][kTileWords<1>];
     const int32_t* tw = reinterpret_cast<const int32_t*>(twfq);
     for (int k = threadIdx.x; k < 2048; k += kBlockThreads) stw[k] = tw[k];
     __syncthreads();
@@ -833,9 +884,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare_q(const uint32_t* 
     bk_residue<1>(bk, poly, t, x1, &tiles[wave][h][0], stw + 1024);
     const uint32_t i = poly / 8, r = (poly / 2) % 4, c = poly % 2;
     const uint32_t hp = r >> 1, digit = r & 1;
-    uint64_t* dst = bkq + (size_t)i * (2 * 32 * 2 * 64) + (size_t)hp * (32 * 2 * 64) + 32 * c + t;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(bkq) + (size_t)i * 16384 + (size_t)hp * 8192 + 32 * c + t;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) dst[(q * 2 + digit) * 64] = pack2(x0[q], x1[q]);
+    for (int q = 0; q < 32; ++q) {
+        dst[(q * 2 + digit) * 64] = (uint32_t)x0[q];
+        dst[4096 + (q * 2 + digit) * 64] = (uint32_t)x1[q];
+    }
 }
 
 // One CMux on acc[2][N] in global memory (single wave).
@@ -843,7 +897,7 @@ template <int A>
 __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bk_i,
                                                    int32_t abar, uint32_t* __restrict__ accg) {
     __shared__ uint64_t stw[2][32 * 32];
-    __shared__ WaveLds W;
+    __shared__ WaveLdsT<kTileWords<A>> W;
     const uint64_t* twf = Arith<A>::twf(K);
     const uint64_t* twi = Arith<A>::twi(K);
     for (int k = threadIdx.x; k < 1024; k += 64) {
@@ -881,6 +935,7 @@ static hipError_t launch_blind_rotate_a(const DeviceKeys& K, const GateIO& io, u
     case 1: hipLaunchKernelGGL((k_blind_rotate<1, A>), dim3(blocks), dim3(64), 0, s, K, io, big, count); break;
     case 2: hipLaunchKernelGGL((k_blind_rotate<2, A>), dim3(blocks), dim3(128), 0, s, K, io, big, count); break;
     case 4: hipLaunchKernelGGL((k_blind_rotate<4, A>), dim3(blocks), dim3(256), 0, s, K, io, big, count); break;
+    case 8: hipLaunchKernelGGL((k_blind_rotate<8, A>), dim3(blocks), dim3(512), 0, s, K, io, big, count); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
