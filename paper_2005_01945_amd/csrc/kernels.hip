@@ -407,30 +407,38 @@ __device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, 
 // Multiply-accumulate of prime I for pass HP: column h of the products of the
 // two digit transforms (r0: digit 0, half 0's; r1: digit 1, half 1's, both
 // obtained with one v_permlane32_swap) with BK rows 2HP and 2HP + 1.
-// bk: the prime-I plane of BK_i for pass HP, [q][digit][64 lanes] words.
-// Key loads run two chunks of four registers ahead of their use; the first
-// two chunks (`pre`) were issued before the forward transform.
-template <int I, bool ACCUM>
-__device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __restrict__ bk,
-                                      uint32_t (&pre)[2][8], int lane, int32_t (&mac)[32]) {
-    uint32_t win[3][8];
+// bk: the prime-I plane of BK_i for pass HP, [q][digit][64 lanes] words, in
+// 8 chunks of 4 registers (8 words).  Key loads run W chunks ahead of their
+// use; the first W chunks (`pre`) were issued before the forward transform.
+template <int W>
+struct KeyWindow {
+    uint32_t w[W + 1 > 8 ? 8 : W + 1][8];
+};
+
+template <int W>
+__device__ __forceinline__ void prefetch_q(const uint32_t* __restrict__ bk, int lane, KeyWindow<W>& kw) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        win[0][k] = pre[0][k];
-        win[1][k] = pre[1][k];
-    }
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) kw.w[c][k] = bk[(c * 8 + k) * 64 + lane];
+}
+
+template <int I, bool ACCUM, int W>
+__device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __restrict__ bk,
+                                      KeyWindow<W>& kw, int lane, int32_t (&mac)[32]) {
+    constexpr int R = W + 1 > 8 ? 8 : W + 1;  // ring slots
     mq::static_for<0, 8>([&](auto C_) {
         constexpr int c = decltype(C_)::value;
-        if constexpr (c + 2 < 8) {
+        if constexpr (c + W < 8) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) win[(c + 2) % 3][k] = bk[((c + 2) * 8 + k) * 64 + lane];
+            for (int k = 0; k < 8; ++k) kw.w[(c + W) % R][k] = bk[((c + W) * 8 + k) * 64 + lane];
         }
         sched_fence();
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int q = 4 * c + j;
             const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)x[q], (uint32_t)x[q], false, false);
-            const int32_t b0 = (int32_t)win[c % 3][2 * j], b1 = (int32_t)win[c % 3][2 * j + 1];
+            const int32_t b0 = (int32_t)kw.w[c % R][2 * j], b1 = (int32_t)kw.w[c % R][2 * j + 1];
             const int32_t v = mq::mont<I>((int64_t)(int32_t)sw[0] * b0 + (int64_t)(int32_t)sw[1] * b1);
             mac[q] = ACCUM ? mac[q] + v : v;
         }
@@ -438,20 +446,13 @@ __device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __
     sched_fence();
 }
 
-template <int I>
-__device__ __forceinline__ void prefetch_q(const uint32_t* __restrict__ bk, int lane, uint32_t (&pre)[2][8]) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) pre[c][k] = bk[(c * 8 + k) * 64 + lane];
-}
-
 // Pass HP of a CMux step with two-prime products (see cmux_pass): digits of
 // ACC_HP (half h: digit h), then for each prime in turn its transform and
 // multiply-accumulate of column h.  The digits wait for the second prime
 // packed two to a register.  mac: low word prime 0, high word prime 1, each
 // |.| < q per pass.  bk_i: BK_i, [hp][prime][q][digit][64 lanes] words.
-template <int HP, bool ACCUM, bool PREFETCH>
+// W: key-load window in chunks (8: all loads issued before the transform).
+template <int HP, bool ACCUM, int W>
 __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, int ai,
                                             const uint64_t* __restrict__ bk_i, const int32_t* twf,
                                             int lane, uint64_t (&mac)[32]) {
@@ -459,8 +460,8 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
     const int shift = 22 - 10 * h;
     const uint32_t* bk0 = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192;
     const uint32_t* bk1 = bk0 + 4096;
-    uint32_t pre[2][8];
-    prefetch_q<0>(bk0, lane, pre);
+    KeyWindow<W> kw;
+    prefetch_q<W>(bk0, lane, kw);
     int32_t x[32];
     uint32_t dp[16];
 #pragma unroll
@@ -489,18 +490,17 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
         }
     }
     ntt1024_fwd_q<0>(x, tile, twf, t);
-    mac_q<0, ACCUM>(x, bk0, pre, lane, m0);
-    prefetch_q<1>(bk1, lane, pre);
+    mac_q<0, ACCUM, W>(x, bk0, kw, lane, m0);
+    prefetch_q<W>(bk1, lane, kw);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         x[2 * j] = (int32_t)(dp[j] << 16) >> 16;
         x[2 * j + 1] = (int32_t)dp[j] >> 16;
     }
     ntt1024_fwd_q<1>(x, tile, twf + 1024, t);
-    mac_q<1, ACCUM>(x, bk1, pre, lane, m1);
+    mac_q<1, ACCUM, W>(x, bk1, kw, lane, m1);
 #pragma unroll
     for (int q = 0; q < 32; ++q) mac[q] = pack2(m0[q], m1[q]);
-    (void)PREFETCH;
 }
 
 // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 -> V mod
@@ -537,12 +537,13 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
     sched_fence();
 }
 
+template <int KW>
 __device__ __forceinline__ void cmux_step_q(WaveLdsT<32 * 33>& W, int ai, const uint64_t* __restrict__ bk_i,
                                             const int32_t* twf, const int32_t* twi, int lane) {
     const int h = lane >> 5;
     uint64_t mac[32];
-    cmux_pass_q<0, false, false>(W.acc[0], W.tile[h], ai, bk_i, twf, lane, mac);
-    cmux_pass_q<1, true, false>(W.acc[1], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_pass_q<0, false, KW>(W.acc[0], W.tile[h], ai, bk_i, twf, lane, mac);
+    cmux_pass_q<1, true, KW>(W.acc[1], W.tile[h], ai, bk_i, twf, lane, mac);
     cmux_finish_q(W.acc, W.tile[h], mac, twi, lane);
     wave_lds_sync();
 }
@@ -557,14 +558,15 @@ struct Arith<0> {
     __host__ __device__ static const uint64_t* bk(const DeviceKeys& K) { return K.bkd; }
     __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twf; }
     __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twi; }
+    template <int KW>
     __device__ __forceinline__ static void step(WaveLds& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
                                 const uint64_t* twi, int lane) {
         cmux_step(W, ai, bk_i, twf, twi, lane);
     }
-    template <int HP, bool PREFETCH>
+    template <int HP, int KW>
     __device__ __forceinline__ static void pass(const uint32_t* a, uint32_t* tile, int ai, const uint64_t* bk_i,
                                 const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
-        cmux_pass<HP, false, PREFETCH>(a, tile, ai, bk_i, twf, lane, mac);
+        cmux_pass<HP, false, true>(a, tile, ai, bk_i, twf, lane, mac);  // (two-wave shape only)
     }
     __device__ __forceinline__ static uint64_t add(uint64_t x, uint64_t y) { return gl::add(x, y); }
     __device__ __forceinline__ static void finish(uint32_t (&acc)[2][1024], uint32_t* tile, uint64_t (&mac)[32],
@@ -578,15 +580,16 @@ struct Arith<1> {
     __host__ __device__ static const uint64_t* bk(const DeviceKeys& K) { return K.bkq; }
     __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twfq; }
     __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twiq; }
+    template <int KW>
     __device__ __forceinline__ static void step(WaveLdsT<32 * 33>& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
                                 const uint64_t* twi, int lane) {
-        cmux_step_q(W, ai, bk_i, reinterpret_cast<const int32_t*>(twf),
+        cmux_step_q<KW>(W, ai, bk_i, reinterpret_cast<const int32_t*>(twf),
                     reinterpret_cast<const int32_t*>(twi), lane);
     }
-    template <int HP, bool PREFETCH>
+    template <int HP, int KW>
     __device__ __forceinline__ static void pass(const uint32_t* a, uint32_t* tile, int ai, const uint64_t* bk_i,
                                 const uint64_t* twf, int lane, uint64_t (&mac)[32]) {
-        cmux_pass_q<HP, false, PREFETCH>(a, tile, ai, bk_i, reinterpret_cast<const int32_t*>(twf), lane, mac);
+        cmux_pass_q<HP, false, KW>(a, tile, ai, bk_i, reinterpret_cast<const int32_t*>(twf), lane, mac);
     }
     __device__ __forceinline__ static uint64_t add(uint64_t x, uint64_t y) {
         return pack2(lo_of(x) + lo_of(y), hi_of(x) + hi_of(y));
@@ -693,6 +696,11 @@ __device__ __forceinline__ void sample_extract(const uint32_t (&acc)[2][1024], u
 // Kernels.
 // ---------------------------------------------------------------------------
 
+// Key-load window (chunks of 8 words ahead) of the two-prime passes.  Two
+// chunks measured best for every shape: issuing all of a pass's key loads
+// before its transform was slower even with the full register file.
+constexpr int kKeyWindow = 2;
+
 // Gate linear combination + modulus switch, test-vector rotation, 500 CMux,
 // sample extraction.  One wave per gate, WPB gates per block; the register
 // budget allows two waves per SIMD.
@@ -718,7 +726,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll 1
     for (int i = 0; i < NLWE; ++i) {
         const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
-        Arith<A>::step(W, ai, bk, S.twf, S.twi, lane);
+        Arith<A>::template step<kKeyWindow>(W, ai, bk, S.twf, S.twi, lane);
         bk += 2 * 32 * 2 * 64;
         if ((i & 63) == 63) {
 #pragma unroll
@@ -755,9 +763,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
         uint64_t mac[32];
         if (wave == 0) {
-            Arith<A>::template pass<0, true>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
+            Arith<A>::template pass<0, kKeyWindow>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
         } else {
-            Arith<A>::template pass<1, true>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
+            Arith<A>::template pass<1, kKeyWindow>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
 #pragma unroll
             for (int q = 0; q < 32; ++q) S.part[q][lane] = mac[q];
         }
@@ -906,7 +914,7 @@ __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t*
     }
     for (int k = threadIdx.x; k < 2 * N; k += 64) W.acc[k / N][k % N] = accg[k];
     __syncthreads();
-    Arith<A>::step(W, abar, bk_i, stw[0], stw[1], threadIdx.x);
+    Arith<A>::template step<kKeyWindow>(W, abar, bk_i, stw[0], stw[1], threadIdx.x);
     __syncthreads();
     for (int k = threadIdx.x; k < 2 * N; k += 64) accg[k] = W.acc[k / N][k % N];
 }
