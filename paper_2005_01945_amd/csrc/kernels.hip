@@ -355,11 +355,16 @@ __device__ __forceinline__ uint64_t pack2(int32_t a, int32_t b) {
 // k holds (row wr(k), col t); after: register k holds (row t, col rd(k)).
 template <class WR, class RD>
 __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
+    uint32_t* col = tile + t;       // this lane's column
+    uint32_t* row = tile + 33 * t;  // this lane's row
+    // Opaque to the optimiser: otherwise it hoists one base address per pair
+    // of reads out of the CMux loop and spills them.
+    asm volatile("" : "+v"(row));
 #pragma unroll
-    for (int k = 0; k < 32; ++k) tile[wr(k) * 33 + t] = (uint32_t)x[k];
+    for (int k = 0; k < 32; ++k) col[wr(k) * 33] = (uint32_t)x[k];
     wave_lds_sync();
 #pragma unroll
-    for (int k = 0; k < 32; ++k) x[k] = (int32_t)tile[t * 33 + rd(k)];
+    for (int k = 0; k < 32; ++k) x[k] = (int32_t)row[rd(k)];
     wave_lds_sync();
 }
 
