@@ -245,25 +245,49 @@ MQ_FN void static_for(F&& f) {
     }
 }
 
+// First butterfly of stage L that uses the same twiddle as butterfly k.
+constexpr int first_same_tw(int kind, int L, int k) {
+    for (int j = 0; j < k; ++j)
+        if (((tw_exp(kind, L, j) - tw_exp(kind, L, k)) % 64) == 0) return j;
+    return k;
+}
+
 // The 32-point transform KIND of the 32 registers x (modulo q_I), inputs
 // bounded by IN q; outputs are bounded by PlanOf<KIND, IN>::value.out_bound q.
+// Each stage first materialises its distinct twiddles (2^L of them, 31 per
+// transform) in scalar registers.
 template <int I, int KIND, int IN>
 MQ_FN void ntt32(int32_t (&x)[32]) {
     using P = PlanOf<KIND, IN>;
     static_for<0, 5>([&](auto L_) {
         constexpr int L = decltype(L_)::value;
         stage_fence();
+        int32_t w[16];
+        static_for<0, 16>([&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int e = ((tw_exp(KIND, L, k) % 64) + 64) % 64;
+            constexpr int f = first_same_tw(KIND, L, k);
+            if constexpr (e != 0 && f == k) w[k] = sconst<Mod<I>::rho.v[e]>();
+            else if constexpr (e != 0) w[k] = w[f];
+        });
+        constexpr bool any_red = [] {
+            for (int k = 0; k < 16; ++k)
+                if (P::value.red_u[L][k] || P::value.red_v[L][k]) return true;
+            return false;
+        }();
+        int32_t one = 0;  // R mod q: a Montgomery product with it reduces
+        if constexpr (any_red) one = sconst<Mod<I>::rform(1)>();
         static_for<0, 16>([&](auto K_) {
             constexpr int k = decltype(K_)::value;
             constexpr int u = bf_u(KIND, L, k), v = bf_v(KIND, L, k);
             constexpr int e = ((tw_exp(KIND, L, k) % 64) + 64) % 64;
             int32_t U = x[u], V = x[v];
             if constexpr (e != 0) {
-                V = mul<I>(V, sconst<Mod<I>::rho.v[e]>());
+                V = mul<I>(V, w[k]);
             } else if constexpr (P::value.red_v[L][k]) {
-                V = reduce<I>(V);
+                V = mul<I>(V, one);
             }
-            if constexpr (P::value.red_u[L][k]) U = reduce<I>(U);
+            if constexpr (P::value.red_u[L][k]) U = mul<I>(U, one);
             x[u] = U + V;
             x[v] = U - V;
         });
