@@ -368,19 +368,42 @@ __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, 
     wave_lds_sync();
 }
 
+// x[B..B+8) *= w[0..8) (Montgomery forms), in three phases (products,
+// quotients, reductions) so that dependent instructions are 8 apart.
+template <int I, int B>
+__device__ __forceinline__ void mul8_q(int32_t (&x)[32], const int32_t (&w)[8]) {
+    int64_t p[8];
+    int32_t m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = (int64_t)x[B + k] * w[k];
+    sched_fence();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<I>::qinv);
+    sched_fence();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[B + k] = (int32_t)((p[k] - (int64_t)m[k] * (int64_t)mq::Mod<I>::q) >> 32);
+    sched_fence();
+}
+
+// Table twiddles: x[q] *= tw[q * 32 + t], eight at a time.
+template <int I>
+__device__ __forceinline__ void table_mul_q(int32_t (&x)[32], const int32_t* tw, int t) {
+    mq::static_for<0, 4>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
+        int32_t w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w[k] = tw[(8 * c + k) * 32 + t];
+        mul8_q<I, 8 * c>(x, w);
+    });
+}
+
 // Forward 1024-point negacyclic NTT modulo q_I of this half's polynomial
 // (|x| < q in); lane t, register r then holds frequency t + 32 brv5(r),
 // bounded by 7 q.
 template <int I>
 __device__ __forceinline__ void ntt1024_fwd_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twf, int t) {
     mq::ntt32<I, mq::kNeg, 1>(x);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        sched_fence();
-#pragma unroll
-        for (int q = 8 * c; q < 8 * c + 8; ++q) x[q] = mq::mul<I>(x[q], twf[q * 32 + t]);
-    }
-    sched_fence();
+    table_mul_q<I>(x, twf, t);
     transpose32_w(x, tile, t, [](int q) { return brv5(q); }, [](int r) { return r; });
     mq::ntt32<I, mq::kCycFwd, 1>(x);
 }
@@ -390,23 +413,19 @@ __device__ __forceinline__ void ntt1024_fwd_q(int32_t (&x)[32], uint32_t* tile, 
 template <int I>
 __device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twi, int t) {
     mq::ntt32<I, mq::kDitInv, 2>(x);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        sched_fence();
-#pragma unroll
-        for (int r = 8 * c; r < 8 * c + 8; ++r) x[r] = mq::mul<I>(x[r], twi[r * 32 + t]);
-    }
-    sched_fence();
+    table_mul_q<I>(x, twi, t);
     transpose32_w(x, tile, t, [](int r) { return r; }, [](int j) { return j; });
     mq::ntt32<I, mq::kCycInv, 1>(x);
     // negacyclic twist psi^(-32 q) of output q = brv5(r): rho^(-q)
-    mq::static_for<0, 32>([&](auto R_) {
-        constexpr int r = decltype(R_)::value;
-        constexpr int e = (64 - brv5(r)) % 64;
-        if constexpr (r % 8 == 0) sched_fence();
-        x[r] = mq::mul<I>(x[r], mq::sconst<mq::Mod<I>::rho.v[e]>());
+    mq::static_for<0, 4>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
+        int32_t w[8];
+        mq::static_for<0, 8>([&](auto K_) {
+            constexpr int r = 8 * c + decltype(K_)::value;
+            w[decltype(K_)::value] = mq::sconst<mq::Mod<I>::rho.v[(64 - brv5(r)) % 64]>();
+        });
+        mul8_q<I, 8 * c>(x, w);
     });
-    sched_fence();
 }
 
 // Multiply-accumulate of prime I for pass HP: column h of the products of the
@@ -439,13 +458,29 @@ __device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __
             for (int k = 0; k < 8; ++k) kw.w[(c + W) % R][k] = bk[((c + W) * 8 + k) * 64 + lane];
         }
         sched_fence();
+        // phases: exchanges, first products, second products, quotients,
+        // reductions (dependent instructions four apart)
+        int32_t d0[4], d1[4], m[4];
+        int64_t p[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int q = 4 * c + j;
-            const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)x[q], (uint32_t)x[q], false, false);
-            const int32_t b0 = (int32_t)kw.w[c % R][2 * j], b1 = (int32_t)kw.w[c % R][2 * j + 1];
-            const int32_t v = mq::mont<I>((int64_t)(int32_t)sw[0] * b0 + (int64_t)(int32_t)sw[1] * b1);
-            mac[q] = ACCUM ? mac[q] + v : v;
+            const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)x[4 * c + j], (uint32_t)x[4 * c + j], false, false);
+            d0[j] = (int32_t)sw[0];
+            d1[j] = (int32_t)sw[1];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[j] = (int64_t)d0[j] * (int32_t)kw.w[c % R][2 * j];
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[j] += (int64_t)d1[j] * (int32_t)kw.w[c % R][2 * j + 1];
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m[j] = (int32_t)((uint32_t)p[j] * mq::Mod<I>::qinv);
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t v = (int32_t)((p[j] - (int64_t)m[j] * (int64_t)mq::Mod<I>::q) >> 32);
+            mac[4 * c + j] = ACCUM ? mac[4 * c + j] + v : v;
         }
     });
     sched_fence();

@@ -277,17 +277,41 @@ MQ_FN void ntt32(int32_t (&x)[32]) {
         }();
         int32_t one = 0;  // R mod q: a Montgomery product with it reduces
         if constexpr (any_red) one = sconst<Mod<I>::rform(1)>();
+        // Montgomery products of the stage in three phases (products,
+        // quotients, reductions), each over all butterflies, so that
+        // dependent instructions are 16 apart.
+        int64_t pv[16], pu[16];
+        int32_t mv[16], mu[16];
         static_for<0, 16>([&](auto K_) {
             constexpr int k = decltype(K_)::value;
             constexpr int u = bf_u(KIND, L, k), v = bf_v(KIND, L, k);
             constexpr int e = ((tw_exp(KIND, L, k) % 64) + 64) % 64;
-            int32_t U = x[u], V = x[v];
-            if constexpr (e != 0) {
-                V = mul<I>(V, w[k]);
-            } else if constexpr (P::value.red_v[L][k]) {
-                V = mul<I>(V, one);
-            }
-            if constexpr (P::value.red_u[L][k]) U = mul<I>(U, one);
+            if constexpr (e != 0) pv[k] = (int64_t)x[v] * w[k];
+            else if constexpr (P::value.red_v[L][k]) pv[k] = (int64_t)x[v] * one;
+            if constexpr (P::value.red_u[L][k]) pu[k] = (int64_t)x[u] * one;
+        });
+        stage_fence();
+        static_for<0, 16>([&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int e = ((tw_exp(KIND, L, k) % 64) + 64) % 64;
+            if constexpr (e != 0 || P::value.red_v[L][k]) mv[k] = (int32_t)((uint32_t)pv[k] * Mod<I>::qinv);
+            if constexpr (P::value.red_u[L][k]) mu[k] = (int32_t)((uint32_t)pu[k] * Mod<I>::qinv);
+        });
+        stage_fence();
+        static_for<0, 16>([&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int u = bf_u(KIND, L, k), v = bf_v(KIND, L, k);
+            constexpr int e = ((tw_exp(KIND, L, k) % 64) + 64) % 64;
+            if constexpr (e != 0 || P::value.red_v[L][k])
+                x[v] = (int32_t)((pv[k] - (int64_t)mv[k] * (int64_t)Mod<I>::q) >> 32);
+            if constexpr (P::value.red_u[L][k])
+                x[u] = (int32_t)((pu[k] - (int64_t)mu[k] * (int64_t)Mod<I>::q) >> 32);
+        });
+        stage_fence();
+        static_for<0, 16>([&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int u = bf_u(KIND, L, k), v = bf_v(KIND, L, k);
+            const int32_t U = x[u], V = x[v];
             x[u] = U + V;
             x[v] = U - V;
         });
