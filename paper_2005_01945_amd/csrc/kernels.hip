@@ -543,18 +543,6 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
     for (int q = 0; q < 32; ++q) mac[q] = pack2(m0[q], m1[q]);
 }
 
-// Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 -> V mod
-// 2^32.  t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t exactly
-// (|v0 + q0 t| < q0 + q0 q1 / 2 and the true V is in range).
-__device__ __forceinline__ uint32_t crt_low32(int32_t v0, int32_t v1) {
-    constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
-    constexpr int32_t c = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
-    int32_t tq = mq::mul<1>(v1 - v0, c);
-    tq += tq < -(q1 / 2) ? q1 : 0;
-    tq -= tq > q1 / 2 ? q1 : 0;
-    return (uint32_t)v0 + (uint32_t)q0 * (uint32_t)tq;
-}
-
 // Inverse NTTs of both columns (half h: column h), CRT, ACC += result.
 __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t* tile,
                                               uint64_t (&mac)[32], const int32_t* twi, int lane) {
@@ -567,14 +555,43 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
     }
     ntt1024_inv_q<0>(x0, tile, twi, t);
     ntt1024_inv_q<1>(x1, tile, twi + 1024, t);
-    uint32_t* mine = acc[h];
+    uint32_t* mine = acc[h] + t;
+    constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
+    constexpr int32_t cq = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
+    // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 ->
+    // V mod 2^32: t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t
+    // exactly (|v0 + q0 t| < q0 + q0 q1 / 2 and V is the only value of that
+    // size in its class).  Eight coefficients at a time, in phases.
+    mq::static_for<0, 4>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
+        int32_t d[8];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+        for (int k = 0; k < 8; ++k) d[k] = x1[8 * c + k] - x0[8 * c + k];
+        sched_fence();
+        int64_t p[8];
+        int32_t m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = (int64_t)d[k] * cq;
         sched_fence();
 #pragma unroll
-        for (int r = 8 * c; r < 8 * c + 8; ++r) mine[t + 32 * brv5(r)] += crt_low32(x0[r], x1[r]);
-    }
-    sched_fence();
+        for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<1>::qinv);
+        sched_fence();
+        uint32_t old[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * c + k)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int32_t tq = (int32_t)((p[k] - (int64_t)m[k] * q1) >> 32);
+            tq += tq < -(q1 / 2) ? q1 : 0;
+            tq -= tq > q1 / 2 ? q1 : 0;
+            d[k] = tq;
+        }
+        sched_fence();
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            mine[32 * brv5(8 * c + k)] = old[k] + (uint32_t)x0[8 * c + k] + (uint32_t)q0 * (uint32_t)d[k];
+        sched_fence();
+    });
 }
 
 template <int KW>
