@@ -175,3 +175,25 @@ def test_noise_variance_over_16k_bootstraps(env):
     log(f"noise mean {mean:.3e}, predicted key-switching bias {bias:.3e}")
     assert abs(mean - bias) < 4 * np.sqrt((var - mean ** 2) / n) + 2e-5
     np.testing.assert_array_equal(sk.decrypt_bits(got), want)
+
+
+def test_wide_ragged_batch_sampled_bit_exact(env):
+    """A 16,385-gate batch (key switching staged through LDS for wide
+    batches, with a last workgroup of one gate): sampled gates, the first
+    and last among them, bit-exact against the oracle, every gate decrypting
+    to its truth table."""
+    sk, ctx, K = env
+    n = 16385
+    ops = workloads.gate_ops(500, n)
+    A = workloads.bits(501, n).astype(int)
+    B = workloads.bits(502, n).astype(int)
+    c0 = sk.encrypt_bits(A, nonce=92_000_000)
+    c1 = sk.encrypt_bits(B, nonce=93_000_000)
+    log(f"wide ragged batch: {n} gates")
+    got = run_batch(ctx, ops, c0, c1)
+    table = np.array([A & B, 1 - (A & B), A | B, 1 - (A | B), A ^ B, 1 - (A ^ B),
+                      (1 - A) & B, A & (1 - B), (1 - A) | B, A | (1 - B)])
+    np.testing.assert_array_equal(sk.decrypt_bits(got), table[ops.astype(int), np.arange(n)])
+    pick = np.array([0, 1, 8191, 16383, 16384])
+    log("oracle: 5 sampled gates")
+    np.testing.assert_array_equal(got[pick], K.bootstrap(ops[pick], c0[pick], c1[pick], threads=5))
