@@ -544,9 +544,12 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
 }
 
 // Inverse NTTs of both columns (half h: column h), CRT, ACC += result.
+__device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
+                                             const int32_t (&x1)[32], int lane);
+
 __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t* tile,
                                               uint64_t (&mac)[32], const int32_t* twi, int lane) {
-    const int h = lane >> 5, t = lane & 31;
+    const int t = lane & 31;
     int32_t x0[32], x1[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
@@ -555,6 +558,14 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
     }
     ntt1024_inv_q<0>(x0, tile, twi, t);
     ntt1024_inv_q<1>(x1, tile, twi + 1024, t);
+    crt_update_q(acc, x0, x1, lane);
+}
+
+// ACC (half h: polynomial h) += the column given by its residues x0, x1
+// (register r: coefficient t + 32 brv5(r)).
+__device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
+                                             const int32_t (&x1)[32], int lane) {
+    const int h = lane >> 5, t = lane & 31;
     uint32_t* mine = acc[h] + t;
     constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
     constexpr int32_t cq = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
@@ -815,6 +826,57 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __syncthreads();
 
     const uint64_t* bk = Arith<A>::bk(K);
+    if constexpr (A == 1) {
+        // Two-prime form: each wave also takes one prime's inverse.  The
+        // waves swap the other prime's partial column sums, wave w
+        // finishes prime w, wave 1 hands its residues to wave 0, and wave 0
+        // recombines and updates ACC.
+        int32_t* part0 = reinterpret_cast<int32_t*>(&S.part[0][0]);  // [32][64]
+        int32_t* part1 = part0 + 32 * 64;
+        const int32_t* twi = reinterpret_cast<const int32_t*>(S.twi);
+#pragma unroll 1
+        for (int i = 0; i < NLWE; ++i) {
+            const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
+            uint64_t mac[32];
+            int32_t x[32];
+            if (wave == 0) {
+                Arith<A>::template pass<0, kKeyWindow>(S.acc[0], S.tile[0][h], ai, bk, S.twf, lane, mac);
+#pragma unroll
+                for (int q = 0; q < 32; ++q) part1[q * 64 + lane] = hi_of(mac[q]);
+            } else {
+                Arith<A>::template pass<1, kKeyWindow>(S.acc[1], S.tile[1][h], ai, bk, S.twf, lane, mac);
+#pragma unroll
+                for (int q = 0; q < 32; ++q) part0[q * 64 + lane] = lo_of(mac[q]);
+            }
+            __syncthreads();  // partials written; both waves done reading ACC
+            if (wave == 0) {
+#pragma unroll
+                for (int q = 0; q < 32; ++q) x[q] = lo_of(mac[q]) + part0[q * 64 + lane];
+                ntt1024_inv_q<0>(x, S.tile[0][h], twi, t);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 32; ++q) x[q] = hi_of(mac[q]) + part1[q * 64 + lane];
+                ntt1024_inv_q<1>(x, S.tile[1][h], twi + 1024, t);
+#pragma unroll
+                for (int r = 0; r < 32; ++r) part1[r * 64 + lane] = x[r];
+            }
+            __syncthreads();  // prime-1 residues written
+            if (wave == 0) {
+                int32_t x1[32];
+#pragma unroll
+                for (int r = 0; r < 32; ++r) x1[r] = part1[r * 64 + lane];
+                crt_update_q(S.acc, x, x1, lane);
+            }
+            __syncthreads();  // ACC updated
+            bk += 2 * 32 * 2 * 64;
+            if ((i & 63) == 63) {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+            }
+        }
+        sample_extract<128>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
+        return;
+    }
 #pragma unroll 1
     for (int i = 0; i < NLWE; ++i) {
         const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
@@ -942,6 +1004,59 @@ __global__ __launch_bounds__(kKsLdsThreads) void k_key_switch_lds(DeviceKeys K, 
         }
     }
     if (!active) return;
+    uint32_t* o = gate_output(io, g);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
+}
+
+// Key switching of narrow batches, for latency: eight waves per gate, wave w
+// summing the rows of coefficients 128w .. 128w + 127; the eight partial
+// sums meet in LDS and wave 0 writes the result.  A gate's key switch then
+// takes about an eighth of the one-wave time (the rows of one wave are
+// fetched one coefficient after another).
+constexpr int kKsSplitWaves = 8;
+constexpr uint32_t kKsSplitMaxGates = 1024;
+
+__global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceKeys K, GateIO io,
+                                                                        const uint32_t* __restrict__ big,
+                                                                        uint32_t count) {
+    __shared__ uint32_t part[kKsSplitWaves][512];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x;
+    if (g >= count) return;  // uniform over the block
+    const uint32_t* src = big + (size_t)g * (N + 1);
+    uint32_t acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = (wave == 0 && 8 * lane + e == NLWE) ? src[N] : 0u;
+    const uint4* zero = reinterpret_cast<const uint4*>(K.zero_row);
+    constexpr int kPerWave = N / kKsSplitWaves;  // 128
+#pragma unroll 1
+    for (int i0 = wave * kPerWave; i0 < (wave + 1) * kPerWave; i0 += 64) {
+        const uint32_t digits = (src[i0 + lane] + (1u << 15)) >> 16;
+#pragma unroll 1
+        for (int l = 0; l < 64; ++l) {
+            const uint32_t dd = __builtin_amdgcn_readlane(digits, l);
+            const size_t rowbase = ((size_t)(i0 + l) * kKsT) * 3;
+#pragma unroll
+            for (int j = 0; j < (int)kKsT; ++j) {
+                const uint32_t d = (dd >> (14 - 2 * j)) & 3u;
+                const uint4* row = d ? reinterpret_cast<const uint4*>(K.ksk + (rowbase + 3 * j + d - 1) * kKskRowWords)
+                                     : zero;
+                const uint4 v0 = row[2 * lane], v1 = row[2 * lane + 1];
+                acc[0] -= v0.x; acc[1] -= v0.y; acc[2] -= v0.z; acc[3] -= v0.w;
+                acc[4] -= v1.x; acc[5] -= v1.y; acc[6] -= v1.z; acc[7] -= v1.w;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) part[wave][8 * lane + e] = acc[e];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 1; w < kKsSplitWaves; ++w)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] += part[w][8 * lane + e];
     uint32_t* o = gate_output(io, g);
 #pragma unroll
     for (int e = 0; e < 8; ++e)
@@ -1093,6 +1208,10 @@ hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32
         const uint32_t per = kKsLdsThreads / 64;
         hipLaunchKernelGGL(k_key_switch_lds, dim3((count + per - 1) / per), dim3(kKsLdsThreads), 0, s, K, io, big,
                            count);
+        return hipGetLastError();
+    }
+    if (count <= kKsSplitMaxGates) {
+        hipLaunchKernelGGL(k_key_switch_split, dim3(count), dim3(64 * kKsSplitWaves), 0, s, K, io, big, count);
         return hipGetLastError();
     }
     const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
