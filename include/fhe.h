@@ -211,7 +211,9 @@ int fhe_ctx_set_graphs(fhe_ctx* ctx, int enable);
 /*     gate, that many ciphertexts per workgroup (throughput shape);        */
 /*   waves_per_gate = 2, gates_per_group = 1: two wavefronts split every    */
 /*     CMux of one gate (latency shape for levels narrower than the chip);  */
-/*   times either NTT arithmetic (arith 0 or 1).                            */
+/*   each of these with either NTT arithmetic (arith 0 or 1);               */
+/*   waves_per_gate = 4, gates_per_group = 1, arith = 1: four wavefronts    */
+/*     per gate, one per (polynomial, prime) (lowest latency).              */
 /* The shape changes only the schedule and the exact arithmetic used to     */
 /* reach the result: every shape computes the same words.  Captured level   */
 /* schedules are recaptured after a change.                                 */

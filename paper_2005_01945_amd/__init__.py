@@ -304,7 +304,7 @@ def fhe_ctx_set_graphs(ctx, enable):
 # Launch shapes of the blind-rotation kernel (the autotuner's search space):
 # (waves_per_gate, gates_per_group, arith), arith 0 = Goldilocks NTT,
 # 1 = two-prime NTT.
-SHAPES = [(w, g, a) for a in (0, 1) for (w, g) in ((1, 1), (1, 2), (1, 4), (1, 8), (2, 1))]
+SHAPES = [(w, g, a) for a in (0, 1) for (w, g) in ((1, 1), (1, 2), (1, 4), (1, 8), (2, 1))] + [(4, 1, 1)]
 
 
 def fhe_ctx_autotune(ctx, max_width=4096, reps=2):

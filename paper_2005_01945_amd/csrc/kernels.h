@@ -51,7 +51,8 @@ hipError_t launch_bk_prepare_q(const uint32_t* bk, uint64_t* bkq, const uint64_t
 // Kernel shape of a blind-rotation launch.  waves_per_gate = 1: one wave
 // bootstraps a gate, gates_per_group in {1, 2, 4, 8} gates share a workgroup
 // (and its twiddle copy in LDS).  waves_per_gate = 2: two waves split each
-// CMux of one gate (one gate per workgroup; gates_per_group is ignored).
+// CMux of one gate (one gate per workgroup; gates_per_group is ignored);
+// waves_per_gate = 4 (arith 1 only): one wave per (polynomial, prime).
 // arith: 0 = NTT over the Goldilocks prime, 1 = NTT modulo two 28-bit
 // primes recombined by CRT.  Every shape gives the same words.
 struct LaunchConfig {

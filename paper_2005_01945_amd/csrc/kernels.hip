@@ -250,6 +250,18 @@ struct PairLds {
     uint64_t part[32][64];               // [register q][lane]
 };
 
+// Shared memory of one gate bootstrapped by four waves (two-prime arithmetic
+// only, 74 KB): wave w = 2 hp + prime runs pass hp in that prime; the pass-1
+// waves hand their column sums to the pass-0 waves through `part`, which
+// finish their prime; wave 1 hands its residues to wave 0, which recombines.
+struct QuadLds {
+    uint64_t twf[32 * 32];
+    uint64_t twi[32 * 32];
+    uint32_t acc[2][1024];
+    uint32_t tile[4][2][32 * 33];  // [wave][half]
+    int32_t part[2][32][64];       // [prime][register][lane]
+};
+
 // Pass HP of a CMux step: D = X^ai ACC_HP - ACC_HP (a = ACC_HP), this half's
 // gadget digit of it (half h extracts digit h), its forward NTT, then the
 // multiply-accumulate against BK_i rows (2HP + h) and (2HP + 1 - h), column h,
@@ -544,6 +556,36 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
 }
 
 // Inverse NTTs of both columns (half h: column h), CRT, ACC += result.
+// One prime's share of pass HP (the four-wave shape): the digits of ACC_HP,
+// their transform modulo q_I and the multiply-accumulate of column h.
+template <int HP, int I, int W>
+__device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, int ai,
+                                             const uint64_t* __restrict__ bk_i, const int32_t* twf,
+                                             int lane, int32_t (&mac)[32]) {
+    const int h = lane >> 5, t = lane & 31;
+    const int shift = 22 - 10 * h;
+    const uint32_t* bk = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192 + I * 4096;
+    KeyWindow<W> kw;
+    prefetch_q<W>(bk, lane, kw);
+    int32_t x[32];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        sched_fence();
+#pragma unroll
+        for (int q = 8 * c; q < 8 * c + 8; ++q) {
+            const int m = t + 32 * q;
+            const int s = (m - ai) & 2047;
+            const uint32_t v = a[s & 1023];
+            const uint32_t rot = (s & 1024) ? 0u - v : v;
+            const uint32_t D = rot - a[m];
+            x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
+        }
+    }
+    sched_fence();
+    ntt1024_fwd_q<I>(x, tile, twf + I * 1024, t);
+    mac_q<I, false, W>(x, bk, kw, lane, mac);
+}
+
 __device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
                                              const int32_t (&x1)[32], int lane);
 
@@ -904,6 +946,70 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     sample_extract<128>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
 }
 
+// Four waves per gate (two-prime arithmetic), for the lowest latency: the
+// critical path of a CMux is one prime's pass, one prime's inverse and the
+// recombination.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_blind_rotate_quad(
+    DeviceKeys K, GateIO io, uint32_t* __restrict__ big, uint32_t count) {
+    __shared__ QuadLds S;
+    load_twiddles<256>(S, K.twfq, K.twiq);
+    const uint32_t g = blockIdx.x;
+    if (g >= count) return;  // uniform over the block
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, h = lane >> 5, t = lane & 31;
+
+    uint32_t ab[8];
+    const int bbar = gate_prologue(io, g, lane, ab);
+    if (wave == 0) acc_init(S.acc, bbar, h, t);
+    __syncthreads();
+
+    const int32_t* twf = reinterpret_cast<const int32_t*>(S.twf);
+    const int32_t* twi = reinterpret_cast<const int32_t*>(S.twi);
+    const uint64_t* bk = K.bkq;
+#pragma unroll 1
+    for (int i = 0; i < NLWE; ++i) {
+        const int ai = __builtin_amdgcn_readlane(ab[0], i & 63);
+        int32_t x[32];
+        uint32_t* tile = S.tile[wave][h];
+        switch (wave) {
+        case 0: cmux_pass_q1<0, 0, kKeyWindow>(S.acc[0], tile, ai, bk, twf, lane, x); break;
+        case 1: cmux_pass_q1<0, 1, kKeyWindow>(S.acc[0], tile, ai, bk, twf, lane, x); break;
+        case 2: cmux_pass_q1<1, 0, kKeyWindow>(S.acc[1], tile, ai, bk, twf, lane, x); break;
+        default: cmux_pass_q1<1, 1, kKeyWindow>(S.acc[1], tile, ai, bk, twf, lane, x); break;
+        }
+        if (wave >= 2) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) S.part[wave - 2][q][lane] = x[q];
+        }
+        __syncthreads();  // pass-1 sums written; all waves done reading ACC
+        if (wave == 0) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) x[q] += S.part[0][q][lane];
+            ntt1024_inv_q<0>(x, tile, twi, t);
+        } else if (wave == 1) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) x[q] += S.part[1][q][lane];
+            ntt1024_inv_q<1>(x, tile, twi + 1024, t);
+#pragma unroll
+            for (int r = 0; r < 32; ++r) S.part[1][r][lane] = x[r];  // (this wave read part[1] above)
+        }
+        __syncthreads();  // prime-1 residues written
+        if (wave == 0) {
+            int32_t x1[32];
+#pragma unroll
+            for (int r = 0; r < 32; ++r) x1[r] = S.part[1][r][lane];
+            crt_update_q(S.acc, x, x1, lane);
+        }
+        __syncthreads();  // ACC updated
+        bk += 2 * 32 * 2 * 64;
+        if ((i & 63) == 63) {
+#pragma unroll
+            for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
+        }
+    }
+    sample_extract<256>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
+}
+
 // Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
 // j-th base-4 digit of a'_i rounded to 16 bits.  One wave per gate; lane l
 // owns output words 8l .. 8l+7 and gathers 2 KB rows with 16-byte loads.
@@ -1192,6 +1298,11 @@ static hipError_t launch_blind_rotate_a(const DeviceKeys& K, const GateIO& io, u
 hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
                                uint32_t count, LaunchConfig cfg, hipStream_t s) {
     if (count == 0) return hipSuccess;
+    if (cfg.waves_per_gate == 4) {
+        if (cfg.arith != 1 || !K.bkq) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_blind_rotate_quad, dim3(count), dim3(256), 0, s, K, io, big, count);
+        return hipGetLastError();
+    }
     if (cfg.waves_per_gate != 1 && cfg.waves_per_gate != 2) return hipErrorInvalidValue;
     if (cfg.arith == 1) {
         if (!K.bkq) return hipErrorInvalidValue;

@@ -20,7 +20,7 @@ namespace fhe {
 namespace {
 
 constexpr dev::LaunchConfig kShapes[] = {{1, 1, 0}, {1, 2, 0}, {1, 4, 0}, {1, 8, 0}, {2, 1, 0},
-                                         {1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {2, 1, 1}};
+                                         {1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {2, 1, 1}, {4, 1, 1}};
 
 bool same(const dev::LaunchConfig& a, const dev::LaunchConfig& b) {
     return a.waves_per_gate == b.waves_per_gate && a.gates_per_group == b.gates_per_group && a.arith == b.arith;
@@ -30,6 +30,7 @@ bool shape_valid(const fhe_launch_config& c) {
     if (c.arith > 1) return false;
     if (c.waves_per_gate == 1)
         return c.gates_per_group == 1 || c.gates_per_group == 2 || c.gates_per_group == 4 || c.gates_per_group == 8;
+    if (c.waves_per_gate == 4) return c.gates_per_group == 1 && c.arith == 1;
     return c.waves_per_gate == 2 && c.gates_per_group == 1;
 }
 
@@ -42,12 +43,13 @@ int tune_bucket(size_t width) {
 }
 
 // Before any measurement (defaults from measurements on MI355X): two-prime
-// arithmetic everywhere; the two-wave shape while all gates fit at two 56 KB
-// workgroups per CU; one wave per SIMD with the full register file (four
-// gates per workgroup, one 81 KB workgroup per CU) up to four gates per CU;
-// eight gates per workgroup (two waves per SIMD) beyond.
+// arithmetic everywhere; four waves per gate up to one gate per CU, two
+// waves per gate up to two; one wave per SIMD with the full register file
+// (four gates per workgroup, one 81 KB workgroup per CU) up to four gates
+// per CU; eight gates per workgroup (two waves per SIMD) beyond.
 static dev::LaunchConfig default_shape(const fhe_ctx* ctx, size_t width) {
     const size_t cus = (size_t)ctx->cu_count;
+    if (width <= cus) return dev::LaunchConfig{4, 1, 1};
     if (width <= 2 * cus) return dev::LaunchConfig{2, 1, 1};
     if (width <= 4 * cus) return dev::LaunchConfig{1, 4, 1};
     return dev::LaunchConfig{1, 8, 1};

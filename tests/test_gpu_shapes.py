@@ -1,7 +1,7 @@
 """Launch shapes and the autotuner: every blind-rotation shape (one wave per
-gate with 1, 2 or 4 gates per workgroup, or two waves per gate; NTT over the
-Goldilocks prime or modulo two 28-bit primes) gives the oracle's words bit
-for bit, and the tuner only ever stores such shapes."""
+gate with 1, 2, 4 or 8 gates per workgroup, or two or four waves per gate;
+NTT over the Goldilocks prime or modulo two 28-bit primes) gives the
+oracle's words bit for bit, and the tuner only ever stores such shapes."""
 import numpy as np
 import pytest
 
@@ -54,7 +54,7 @@ def test_every_shape_bit_exact(env):
         F.fhe_ctx_set_launch_config(ctx, 1, WIDEST, (1, 4, 0))
 
 
-@pytest.mark.parametrize("shape", [(2, 1, 0), (2, 1, 1), (1, 4, 1)])
+@pytest.mark.parametrize("shape", [(2, 1, 0), (2, 1, 1), (1, 4, 1), (4, 1, 1)])
 def test_shape_on_circuit_output(env, shape):
     """Gates whose inputs are themselves gate outputs (noisier, key-switched
     samples), against the oracle."""
@@ -79,7 +79,7 @@ def test_shape_ranges_and_errors(env):
     F.fhe_ctx_set_launch_config(ctx, 1, 8, (2, 1, 1))
     assert [F.fhe_ctx_launch_config(ctx, w) for w in (1, 5, 8, 9, 1 << 20)] == \
         [(2, 1, 1), (2, 1, 1), (2, 1, 1), (1, 4, 0), (1, 4, 0)]
-    for bad in [(1, 3, 0), (2, 2, 0), (3, 1, 0), (0, 1, 0), (1, 4, 2)]:
+    for bad in [(1, 3, 0), (2, 2, 0), (3, 1, 0), (0, 1, 0), (1, 4, 2), (4, 1, 0), (4, 2, 1)]:
         with pytest.raises(F.FheError):
             F.fhe_ctx_set_launch_config(ctx, 1, 4, bad)
     with pytest.raises(F.FheError):
