@@ -143,6 +143,8 @@ __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0
 // Orders the wave's LDS traffic: LDS operations of one wavefront execute in
 // issue order, so a compiler-level barrier is all a wave-private exchange
 // needs.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -367,10 +369,12 @@ __device__ __forceinline__ uint64_t pack2(int32_t a, int32_t b) {
 // k holds (row wr(k), col t); after: register k holds (row t, col rd(k)).
 template <class WR, class RD>
 __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
-    uint32_t* col = tile + t;       // this lane's column
-    uint32_t* row = tile + 33 * t;  // this lane's row
-    // Opaque to the optimiser: otherwise it hoists one base address per pair
-    // of reads out of the CMux loop and spills them.
+    uint32_t* col = tile + t;  // this lane's column
+    // This lane's row, as an LDS address opaque to the optimiser: otherwise
+    // it hoists one base address per pair of reads out of the CMux loop and
+    // spills them.  (Kept in the LDS address space so that the reads are LDS
+    // instructions, which wait on LDS traffic only.)
+    lds_u32* row = (lds_u32*)(tile + 33 * t);
     asm volatile("" : "+v"(row));
 #pragma unroll
     for (int k = 0; k < 32; ++k) col[wr(k) * 33] = (uint32_t)x[k];
