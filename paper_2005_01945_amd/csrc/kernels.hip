@@ -145,6 +145,15 @@ __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0
 // needs.
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
+// Word t of an LDS array as an LDS address the optimiser cannot see through,
+// so that the 32 reads at t + 32 q share one base register held in the loop
+// (otherwise it hoists a base per pair of reads and spills them).
+__device__ __forceinline__ const lds_u32* lds_column(const uint32_t* a, int t) {
+    const lds_u32* p = (const lds_u32*)(a + t);
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -514,6 +523,7 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
                                             int lane, uint64_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
+    const lds_u32* am = lds_column(a, t);
     const uint32_t* bk0 = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192;
     const uint32_t* bk1 = bk0 + 4096;
     KeyWindow<W> kw;
@@ -529,7 +539,7 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
             const int s = (m - ai) & 2047;
             const uint32_t v = a[s & 1023];
             const uint32_t rot = (s & 1024) ? 0u - v : v;
-            const uint32_t D = rot - a[m];
+            const uint32_t D = rot - am[32 * q];
             x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
         }
 #pragma unroll
@@ -568,6 +578,7 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
                                              int lane, int32_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
+    const lds_u32* am = lds_column(a, t);
     const uint32_t* bk = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192 + I * 4096;
     KeyWindow<W> kw;
     prefetch_q<W>(bk, lane, kw);
@@ -581,7 +592,7 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
             const int s = (m - ai) & 2047;
             const uint32_t v = a[s & 1023];
             const uint32_t rot = (s & 1024) ? 0u - v : v;
-            const uint32_t D = rot - a[m];
+            const uint32_t D = rot - am[32 * q];
             x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
         }
     }
