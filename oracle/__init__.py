@@ -80,6 +80,7 @@ def lib():
             "or_bootstrap_gates": (None, [KP, u8p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_circuit_add": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_mul": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_mul_tree": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_gate_count": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32]),
         }
@@ -231,6 +232,14 @@ class Keys:
         lib().or_circuit_mul(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
+    def mul_tree(self, A, B, width: int, threads: int = 0) -> np.ndarray:
+        """Low width bits of A*B, partial products summed by a tree (Sec. V-B-2)."""
+        a = _c(A, np.uint32).reshape(-1, width, self.width)
+        b = _c(B, np.uint32).reshape(-1, width, self.width)
+        out = np.empty_like(a)
+        lib().or_circuit_mul_tree(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
     def matvec(self, M, x, rows: int, cols: int, width: int, threads: int = 0) -> np.ndarray:
         m = _c(M, np.uint32).reshape(rows, cols, width, self.width)
         v = _c(x, np.uint32).reshape(cols, width, self.width)
@@ -287,5 +296,5 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
-    k = {"add": 0, "mul": 1, "matvec": 2}[kind]
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)

@@ -521,6 +521,52 @@ static void build_mul(or_prog* pr, const long* a, const long* b, int w, long* r)
     free(sum);
 }
 
+/* Multiplication with tree accumulation (Sec. V-B-2, "Multiplication"; Fig. 4),
+ * low w bits.  Partial product i is (A & b_i) shifted left by i: its bits
+ * i..w-1 are the gates a_j & b_i for j = 0..w-1-i, its bits below i are zero
+ * and carry no wire.  The list of the w partial products is split into its
+ * first and second halves, which are added element-wise; an odd last element
+ * waits a round; the rounds repeat until one number is left.  Adding a
+ * number whose known-zero low bits end at l to one whose end at m > l copies
+ * bits l..m-1 of the first and ripple-adds (eqs. (1)-(2), carry out dropped)
+ * bits m..w-1 of both. */
+static void build_mul_tree(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    long* bits = (long*)malloc((size_t)w * w * sizeof(long)); /* number k: bits[k*w + pos] */
+    int* low = (int*)malloc((size_t)w * sizeof(int));         /* first wired bit of number k */
+    long* sum = (long*)malloc((size_t)w * sizeof(long));
+    for (int i = 0; i < w; i++) {
+        low[i] = i;
+        for (int j = 0; i + j < w; j++) bits[(size_t)i * w + i + j] = emit(pr, OR_AND, a[j], b[i]);
+    }
+    int len = w;
+    while (len > 1) {
+        int h = len / 2;
+        for (int k = 0; k < h; k++) {
+            long* x = bits + (size_t)k * w;
+            long* y = bits + (size_t)(k + h) * w;
+            int lx = low[k], ly = low[k + h];
+            if (ly < lx) { /* keep x the one with fewer known-zero bits */
+                long* t = x; x = y; y = t;
+                int u = lx; lx = ly; ly = u;
+            }
+            build_add(pr, x + ly, y + ly, w - ly, sum);
+            long* dst = bits + (size_t)k * w;
+            for (int p = lx; p < ly; p++) dst[p] = x[p];
+            for (int p = ly; p < w; p++) dst[p] = sum[p - ly];
+            low[k] = lx;
+        }
+        if (len & 1) {
+            memcpy(bits + (size_t)h * w, bits + (size_t)(len - 1) * w, (size_t)w * sizeof(long));
+            low[h] = low[len - 1];
+        }
+        len = h + (len & 1);
+    }
+    memcpy(r, bits, (size_t)w * sizeof(long));
+    free(bits);
+    free(low);
+    free(sum);
+}
+
 /* Tree accumulation (Sec. V-B-2, Fig. 4): the list is split into its first
  * and second halves, which are added element-wise; an odd last element is
  * carried to the next round unchanged. */
@@ -576,7 +622,7 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     free(o);
 }
 
-enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2 };
+enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
@@ -592,6 +638,7 @@ static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const 
             ib[k] = (long)((count + c) * width + k);
         }
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, outw + c * width);
+        else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, outw + c * width);
         else build_mul(&pr, ia, ib, width, outw + c * width);
     }
     uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
@@ -617,7 +664,12 @@ void or_circuit_mul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint
     circuit_binary(K, KIND_MUL, A, B, R, count, width, threads);
 }
 
-/* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the multiplier above,
+void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                         size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_MUL_TREE, A, B, R, count, width, threads);
+}
+
+/* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the shift-and-add multiplier,
  * each row's products summed by the tree above. */
 static void build_matvec(or_prog* pr, int32_t rows, int32_t cols, int32_t w, long* yw) {
     long* prods = (long*)malloc((size_t)cols * w * sizeof(long));
@@ -669,6 +721,7 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
         for (int32_t k = 0; k < width; k++) { ia[k] = k; ib[k] = width + k; }
         pr.nwires = 2L * width;
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, r);
+        else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, r);
         else build_mul(&pr, ia, ib, width, r);
         free(ia);
         free(ib);

@@ -108,9 +108,14 @@ void or_circuit_add(const or_keys* K, const uint32_t* A, const uint32_t* B, uint
                     size_t count, int32_t width, int threads);
 void or_circuit_mul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                     size_t count, int32_t width, int threads);
+/* Low width bits of A*B with the partial products accumulated by a tree
+ * (Sec. V-B-2): same gates as or_circuit_mul, fewer levels. */
+void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                         size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
-/* Number of bootstrapped gates the circuits above evaluate (no evaluation). */
+/* Number of bootstrapped gates the circuits above evaluate (no evaluation);
+ * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation. */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

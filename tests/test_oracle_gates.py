@@ -141,6 +141,16 @@ def test_mul_circuit_decrypts_to_low_product(okeys):
     np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a * b) % (1 << w))
 
 
+def test_mul_tree_circuit_decrypts_to_low_product(okeys):
+    """Tree accumulation of the partial products (Sec. V-B-2): the product's
+    low bits, with carries across every round and a wrap past 2^w."""
+    w = 5
+    a = np.array([29, 23], np.uint64)
+    b = np.array([27, 22], np.uint64)
+    R = okeys.mul_tree(okeys.encrypt_uint(a, w, nonce=72_000), okeys.encrypt_uint(b, w, nonce=82_000), w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a * b) % (1 << w))
+
+
 def test_matvec_circuit_decrypts_to_product(okeys):
     w, rows, cols = 2, 2, 2
     M = np.array([[3, 2], [1, 3]], np.uint64)
@@ -163,3 +173,13 @@ def test_circuit_gate_counts():
     assert oracle.circuit_gate_count("mul", 32) == ands + adders == 2824
     assert oracle.circuit_gate_count("mul", 16) == 648
     assert oracle.circuit_gate_count("matvec", 16, 64, 64) == 4096 * 648 + 64 * 63 * 74
+
+
+def test_mul_tree_gate_count_equals_shift_and_add():
+    """Every partial product i >= 1 is the operand with more known-zero low
+    bits in exactly one tree addition, which then spans bits i..w-1, as in the
+    shift-and-add multiplier: the two circuits have the same gates."""
+    add = lambda m: 1 if m == 1 else 5 * m - 6
+    for w in range(1, 40):
+        want = w * (w + 1) // 2 + sum(add(w - i) for i in range(1, w))
+        assert oracle.circuit_gate_count("mul_tree", w) == want == oracle.circuit_gate_count("mul", w)
