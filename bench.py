@@ -338,26 +338,35 @@ def main():
                  "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "gates": len(lat)}
         log(f"plain: {plain}")
 
-    # latency of one 32-bit multiplication (one pair, 120 levels)
-    mul = None
+    # latency of one 32-bit multiplication: shift-and-add (120 levels) and with
+    # the partial products summed by a tree (62 levels), same 2,824 gates
+    mul = mul_tree = None
     if args.mul_samples > 0:
         ma = workloads.uniform_uints(11, 1, 32)
         mb = workloads.uniform_uints(12, 1, 32)
         mA = F.to_device(sk.encrypt_uint(ma, 32, nonce=1 << 52))
         mB = F.to_device(sk.encrypt_uint(mb, 32, nonce=(1 << 52) + 64))
         mR = torch.empty_like(mA)
-        F.fhe_mul(ctx, mA, mB, mR, 1, 32, stream)
-        torch.cuda.synchronize()
-        ml = []
-        for _ in range(args.mul_samples):
-            s0 = time.perf_counter()
-            F.fhe_mul(ctx, mA, mB, mR, 1, 32, stream)
+
+        def mul_latency(fn, kind):
+            fn(ctx, mA, mB, mR, 1, 32, stream)
             torch.cuda.synchronize()
-            ml.append(time.perf_counter() - s0)
-        assert sk.decrypt_uint(F.to_host(mR), 32)[0] == (int(ma[0]) * int(mb[0])) % (1 << 32)
-        mul = {"p50_ms": round(1e3 * float(np.median(ml)), 1), "p99_ms": round(1e3 * float(np.percentile(ml, 99)), 1),
-               "samples": len(ml), "gates": F.fhe_circuit_shape("mul", 32)[0]}
+            ml = []
+            for _ in range(args.mul_samples):
+                s0 = time.perf_counter()
+                fn(ctx, mA, mB, mR, 1, 32, stream)
+                torch.cuda.synchronize()
+                ml.append(time.perf_counter() - s0)
+            assert sk.decrypt_uint(F.to_host(mR), 32)[0] == (int(ma[0]) * int(mb[0])) % (1 << 32)
+            gates, levels, _ = F.fhe_circuit_shape(kind, 32)
+            return {"p50_ms": round(1e3 * float(np.median(ml)), 1),
+                    "p99_ms": round(1e3 * float(np.percentile(ml, 99)), 1),
+                    "samples": len(ml), "gates": gates, "levels": levels}
+
+        mul = mul_latency(F.fhe_mul, "mul")
         log(f"mul32 latency: {mul}")
+        mul_tree = mul_latency(F.fhe_mul_tree, "mul_tree")
+        log(f"mul32 (tree accumulation) latency: {mul_tree}")
 
     serving = None
     if args.serve_jobs > 0:
@@ -380,7 +389,7 @@ def main():
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": workload,
-        "plain": plain, "mul32_latency": mul, "serving": serving,
+        "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": per_shape},

@@ -188,7 +188,17 @@ int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, siz
 int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
             uint32_t width, void* stream);
 
-/* y = M x mod 2^width: every product by the multiplier above, each row summed
+/* R = (A * B) mod 2^width with the partial products (A & b_i) << i summed by
+ * a tree (Sec. V-B-2, "Multiplication", Fig. 4): the list is split into its
+ * first and second halves, added element-wise, until one number is left.
+ * Same gates as fhe_mul (2,824 at width 32), fewer levels (62 instead of
+ * 120), so lower latency; the output words differ from fhe_mul's (other
+ * gates produce them) but decrypt to the same product.  Buffers and errors
+ * as fhe_mul. */
+int fhe_mul_tree(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                 uint32_t width, void* stream);
+
+/* y = M x mod 2^width: every product by the shift-and-add multiplier, each row summed
  * by a tree of adders (Sec. V-B-2, Fig. 4: split in halves, add pairwise).
  * M: device uint32[rows][cols][width][n+1]; x: [cols][width][n+1];
  * y: [rows][width][n+1]. */
@@ -243,7 +253,8 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
                               const fhe_launch_config* cfg);
 
 /* Number of gates and of levels of a circuit as the library schedules it
- * (kind 0 = add, 1 = mul, 2 = matvec; rows/cols only for matvec). */
+ * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation;
+ * rows/cols only for matvec). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 
@@ -260,13 +271,13 @@ int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
 /* ---------------------------------------------------------------------- */
 typedef struct fhe_server fhe_server;
 
-typedef enum { FHE_JOB_GATE = 0, FHE_JOB_ADD = 1, FHE_JOB_MUL = 2, FHE_JOB_MATVEC = 3 } fhe_job_kind;
+typedef enum { FHE_JOB_GATE = 0, FHE_JOB_ADD = 1, FHE_JOB_MUL = 2, FHE_JOB_MATVEC = 3, FHE_JOB_MUL_TREE = 4 } fhe_job_kind;
 
 /* One job.  Buffers are DEVICE memory owned by the caller; inputs must be
  * written (their stream synchronized) before submission and stay valid, and
  * `out` is written when the job reaches FHE_JOB_DONE.
  *   GATE:   in0, in1 [1][n+1], op = gate code, out [1][n+1]
- *   ADD/MUL: in0, in1, out [width][n+1] (one integer, LSB first)
+ *   ADD/MUL/MUL_TREE: in0, in1, out [width][n+1] (one integer, LSB first)
  *   MATVEC: in0 = M [rows][cols][width][n+1], in1 = x [cols][width][n+1],
  *           out = y [rows][width][n+1]                                        */
 typedef struct {

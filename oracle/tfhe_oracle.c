@@ -415,10 +415,11 @@ static void* gate_worker(void* arg) {
     return NULL;
 }
 
+/* threads <= 0: one per online processor, at most 16. */
 static int resolve_threads(int threads) {
     if (threads > 0) return threads;
     long c = sysconf(_SC_NPROCESSORS_ONLN);
-    return c > 0 ? (int)c : 1;
+    return c > 16 ? 16 : c > 0 ? (int)c : 1;
 }
 
 /* Runs gate g on (in0[g], in1[g]) -> out[g] for g < count, pointer form. */

@@ -66,6 +66,7 @@ _SIGS = {
     "fhe_bootstrap_gate_plain": (C.c_int, [_vp, C.c_uint8, _vp, _vp, _vp, _vp]),
     "fhe_add": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_mul_tree": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
@@ -279,14 +280,18 @@ def fhe_mul(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_mul(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_mul")
 
 
+def fhe_mul_tree(ctx, A, B, R, count, width, stream=None):
+    _check(lib().fhe_mul_tree(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_mul_tree")
+
+
 def fhe_matvec(ctx, M, x, y, rows, cols, width, stream=None):
     _check(lib().fhe_matvec(ctx.h, _dev(M), _dev(x), _dev(y), rows, cols, width, _stream(stream)),
            "fhe_matvec")
 
 
 def fhe_circuit_shape(kind, width, rows=0, cols=0):
-    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec'}."""
-    k = {"add": 0, "mul": 1, "matvec": 2}[kind]
+    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree'}."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3}[kind]
     g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")
@@ -346,7 +351,7 @@ def fhe_ctx_timing(ctx):
 # ---------------------------------------------------------------------------
 # Serving
 # ---------------------------------------------------------------------------
-FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC = range(4)
+FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC, FHE_JOB_MUL_TREE = range(5)
 FHE_JOB_QUEUED, FHE_JOB_RUNNING, FHE_JOB_DONE, FHE_JOB_CANCELLED, FHE_JOB_FAILED = range(5)
 
 

@@ -7,7 +7,7 @@
 
 namespace fhe {
 
-enum Kind { kAdd = 0, kMul = 1, kMatvec = 2 };
+enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3 };
 
 struct Gate {
     uint8_t op;
@@ -24,8 +24,8 @@ struct Circuit {
     uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
 };
 
-// kind: kAdd / kMul (operands of width w) or kMatvec (rows x cols matrix of
-// w-bit entries times a cols-vector).
+// kind: kAdd / kMul / kMulTree (operands of width w) or kMatvec (rows x cols
+// matrix of w-bit entries times a cols-vector).
 Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols);
 
 // ASAP level of every gate (inputs are level 0); *depth = deepest level.

@@ -8,6 +8,13 @@
 //      bit w-1:   t = a^b,            r = t^c      (carry out dropped)
 //  - mul, low w bits: naive shift-and-add (Sec. III-B-1):
 //      acc = A & b_0;  acc[i..w-1] += (A & b_i)[0..w-1-i] for i = 1..w-1
+//  - mul with tree accumulation (Sec. V-B-2, Fig. 4), low w bits: partial
+//    product i = (A & b_i) << i carries wires for bits i..w-1 only; the list
+//    of partial products is split into first and second halves added
+//    element-wise (an odd last element waits a round) until one is left.
+//    Adding numbers whose known-zero low bits end at l < m copies bits
+//    l..m-1 of the first and ripple-adds bits m..w-1.  Same gates as mul,
+//    depth 62 instead of 120 at w = 32.
 //  - matvec: every product by mul; each row's products accumulated by the
 //    tree of Sec. V-B-2 / Fig. 4: the list is split into first and second
 //    halves that are added element-wise, an odd last element waits a round.
@@ -76,6 +83,37 @@ class Builder {
         }
         return acc;
     }
+    std::vector<uint32_t> mul_tree(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t w = a.size();
+        struct Part {
+            size_t low;                  // bits below `low` are known zero
+            std::vector<uint32_t> bits;  // wires of bits low..w-1
+        };
+        std::vector<Part> parts;
+        for (size_t i = 0; i < w; ++i) {
+            Part p{i, std::vector<uint32_t>(w - i)};
+            for (size_t j = 0; j + i < w; ++j) p.bits[j] = gate(FHE_AND, a[j], b[i]);
+            parts.push_back(std::move(p));
+        }
+        while (parts.size() > 1) {
+            const size_t h = parts.size() / 2;
+            std::vector<Part> next;
+            for (size_t k = 0; k < h; ++k) {
+                const Part* x = &parts[k];
+                const Part* y = &parts[k + h];
+                if (y->low < x->low) std::swap(x, y);
+                const size_t skip = y->low - x->low;
+                const std::vector<uint32_t> hi(x->bits.begin() + skip, x->bits.end());
+                const std::vector<uint32_t> s = add(hi, y->bits);
+                Part z{x->low, std::vector<uint32_t>(x->bits.begin(), x->bits.begin() + skip)};
+                z.bits.insert(z.bits.end(), s.begin(), s.end());
+                next.push_back(std::move(z));
+            }
+            if (parts.size() & 1) next.push_back(std::move(parts.back()));
+            parts.swap(next);
+        }
+        return parts.empty() ? std::vector<uint32_t>() : parts[0].bits;
+    }
     std::vector<uint32_t> tree_sum(std::vector<std::vector<uint32_t>> vals) {
         while (vals.size() > 1) {
             const size_t h = vals.size() / 2;
@@ -110,7 +148,7 @@ Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
     }
     Builder B(w, w);
     const std::vector<uint32_t> a = iota_wires(0, w), b = iota_wires(w, w);
-    B.c.outputs = kind == kAdd ? B.add(a, b) : B.mul(a, b);
+    B.c.outputs = kind == kAdd ? B.add(a, b) : kind == kMulTree ? B.mul_tree(a, b) : B.mul(a, b);
     return B.c;
 }
 
@@ -342,6 +380,11 @@ extern "C" int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint3
     return run_circuit(ctx, kMul, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul");
 }
 
+extern "C" int fhe_mul_tree(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                            uint32_t width, void* stream) {
+    return run_circuit(ctx, kMulTree, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul_tree");
+}
+
 extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
                           uint32_t cols, uint32_t width, void* stream) {
     if (rows == 0 || cols == 0) return set_error(FHE_EINVAL, "fhe_matvec: empty matrix");
@@ -350,7 +393,7 @@ extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, ui
 
 extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,
                                  uint32_t* levels, uint64_t* widest_level) {
-    if (kind < 0 || kind > 2 || width < 1 || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
+    if (kind < 0 || kind > 3 || width < 1 || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
         return set_error(FHE_EINVAL, "fhe_circuit_shape: bad arguments");
     const Circuit c = build_circuit(kind, width, rows, cols);
     uint32_t depth = 0;

@@ -56,7 +56,10 @@ ServeShape make_shape(int kind, uint32_t op, uint32_t w, uint32_t rows, uint32_t
         S.levels = {{0}};
         return S;
     }
-    const int ck = kind == FHE_JOB_ADD ? kAdd : kind == FHE_JOB_MUL ? kMul : kMatvec;
+    const int ck = kind == FHE_JOB_ADD        ? kAdd
+                   : kind == FHE_JOB_MUL      ? kMul
+                   : kind == FHE_JOB_MUL_TREE ? kMulTree
+                                              : kMatvec;
     const Circuit c = build_circuit(ck, w, rows, cols);
     uint32_t depth = 0;
     const std::vector<uint32_t> glev = asap_levels(c, &depth);
@@ -338,7 +341,7 @@ extern "C" int fhe_serve_create(fhe_ctx* ctx, size_t hbm_budget_bytes, fhe_serve
 extern "C" int fhe_serve_submit(fhe_server* S, const fhe_job* job, uint64_t* ticket) {
     if (!S || !job || !ticket) return set_error(FHE_EINVAL, "fhe_serve_submit: null argument");
     const fhe_job& j = *job;
-    if (j.kind > FHE_JOB_MATVEC) return set_error(FHE_EINVAL, "fhe_serve_submit: job kind %u", j.kind);
+    if (j.kind > FHE_JOB_MUL_TREE) return set_error(FHE_EINVAL, "fhe_serve_submit: job kind %u", j.kind);
     if (j.kind == FHE_JOB_GATE && j.op > FHE_ORYN) return set_error(FHE_EINVAL, "fhe_serve_submit: gate code %u", j.op);
     if (j.kind != FHE_JOB_GATE && (j.width < 1 || j.width > 64))
         return set_error(FHE_EINVAL, "fhe_serve_submit: width %u", j.width);

@@ -92,6 +92,42 @@ def test_add16_full_size(env):
     np.testing.assert_array_equal(got[0], K.add(ca[:1], cb[:1], wl.width)[0])
 
 
+@pytest.mark.parametrize("width,count", [(1, 1), (5, 2), (8, 3)])
+def test_mul_tree_bit_exact(env, width, count):
+    """Tree accumulation of the partial products (Sec. V-B-2)."""
+    sk, ctx, K = env
+    a = workloads.uniform_uints(50 + width, count, width)
+    b = workloads.uniform_uints(60 + width, count, width)
+    ca = sk.encrypt_uint(a, width, nonce=500_000)
+    cb = sk.encrypt_uint(b, width, nonce=600_000)
+    log(f"mul_tree width={width} count={count}")
+    got = gpu_binary(ctx, F.fhe_mul_tree, ca, cb, count, width)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, width), (a * b) % (1 << width))
+    np.testing.assert_array_equal(got, K.mul_tree(ca, cb, width))
+
+
+def test_mul_tree32_decrypts_and_mul_tree16_bit_exact(env):
+    """64 pairs of uniform uint32 through the 62-level tree multiplier decrypt
+    to the low product; a 16-bit tree product is bit-exact end to end."""
+    sk, ctx, K = env
+    a = workloads.uniform_uints(80, 64, 32)
+    b = workloads.uniform_uints(81, 64, 32)
+    ca = sk.encrypt_uint(a, 32, nonce=900_000)
+    cb = sk.encrypt_uint(b, 32, nonce=1_000_000)
+    log("mul_tree32 x 64 pairs")
+    got = gpu_binary(ctx, F.fhe_mul_tree, ca, cb, 64, 32)
+    want = (a.astype(object) * b.astype(object)) % (1 << 32)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, 32).astype(object), want)
+    a16 = workloads.uniform_uints(82, 1, 16)
+    b16 = workloads.uniform_uints(83, 1, 16)
+    c16a = sk.encrypt_uint(a16, 16, nonce=1_100_000)
+    c16b = sk.encrypt_uint(b16, 16, nonce=1_200_000)
+    log("mul_tree16 x 1 pair")
+    got16 = gpu_binary(ctx, F.fhe_mul_tree, c16a, c16b, 1, 16)
+    log("oracle: mul_tree16 (648 gates)")
+    np.testing.assert_array_equal(got16, K.mul_tree(c16a, c16b, 16))
+
+
 def test_mul32_full_size_decrypts(env):
     """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
     product decrypts correctly."""

@@ -24,7 +24,8 @@ def env():
 
 
 def make_jobs(sk):
-    """A small mix: two gates, an add16, an add32, a mul8 and a 2x3 4-bit matvec."""
+    """A small mix: two gates, an add16, an add32, a mul8 (shift-and-add and
+    tree accumulation) and a 2x3 4-bit matvec."""
     import torch
     jobs = []
     nonce = 3_000_000
@@ -34,7 +35,7 @@ def make_jobs(sk):
         jobs.append(dict(kind=F.FHE_JOB_GATE, op=op, a=a, b=b, shape=(1, F.WORDS),
                          want=[[1 - (k & 1), (k & 1) ^ 1][k]], width=1))
     for kind, w, x, y in [(F.FHE_JOB_ADD, 16, 51234, 40000), (F.FHE_JOB_ADD, 32, 4000000000, 500000000),
-                          (F.FHE_JOB_MUL, 8, 201, 77)]:
+                          (F.FHE_JOB_MUL, 8, 201, 77), (F.FHE_JOB_MUL_TREE, 8, 201, 77)]:
         a = sk.encrypt_uint([x], w, nonce=nonce); nonce += w
         b = sk.encrypt_uint([y], w, nonce=nonce); nonce += w
         res = (x + y) % (1 << w) if kind == F.FHE_JOB_ADD else (x * y) % (1 << w)

@@ -119,9 +119,13 @@ def test_circuit_shapes_match_oracle_gate_counts():
     for w in (1, 2, 5, 16, 32):
         assert F.fhe_circuit_shape("add", w)[0] == oracle.circuit_gate_count("add", w)
         assert F.fhe_circuit_shape("mul", w)[0] == oracle.circuit_gate_count("mul", w)
+        assert F.fhe_circuit_shape("mul_tree", w)[0] == oracle.circuit_gate_count("mul_tree", w)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64)[0] == oracle.circuit_gate_count("matvec", 16, 64, 64)
     assert F.fhe_circuit_shape("matvec", 3, 5, 7)[0] == oracle.circuit_gate_count("matvec", 3, 5, 7)
     # gates, ASAP depth, widest level of the paper-sized circuits
     assert F.fhe_circuit_shape("add", 16) == (74, 30, 31)
     assert F.fhe_circuit_shape("mul", 32) == (2824, 120, 528)
+    # tree accumulation: five rounds of additions whose ripple carries overlap
+    assert F.fhe_circuit_shape("mul_tree", 32) == (2824, 62, 528)
+    assert [F.fhe_circuit_shape("mul_tree", w)[1] for w in (8, 16)] == [14, 30]
     assert F.fhe_circuit_shape("matvec", 16, 64, 64) == (2952576, 68, 557056)
