@@ -620,45 +620,59 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
 
 // ACC (half h: polynomial h) += the column given by its residues x0, x1
 // (register r: coefficient t + 32 brv5(r)).
-__device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
-                                             const int32_t (&x1)[32], int lane) {
+// Registers 8C..8C+7 of the CRT update below (x0, x1: those registers'
+// residues).
+template <int C>
+__device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[8],
+                                            const int32_t (&x1)[8], int lane) {
     const int h = lane >> 5, t = lane & 31;
     uint32_t* mine = acc[h] + t;
     constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
     constexpr int32_t cq = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
-    // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 ->
-    // V mod 2^32: t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t
-    // exactly (|v0 + q0 t| < q0 + q0 q1 / 2 and V is the only value of that
-    // size in its class).  Eight coefficients at a time, in phases.
+    int32_t d[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[k] = x1[k] - x0[k];
+    sched_fence();
+    int64_t p[8];
+    int32_t m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = (int64_t)d[k] * cq;
+    sched_fence();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<1>::qinv);
+    sched_fence();
+    uint32_t old[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * C + k)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int32_t tq = (int32_t)((p[k] - (int64_t)m[k] * q1) >> 32);
+        tq += tq < -(q1 / 2) ? q1 : 0;
+        tq -= tq > q1 / 2 ? q1 : 0;
+        d[k] = tq;
+    }
+    sched_fence();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mine[32 * brv5(8 * C + k)] = old[k] + (uint32_t)x0[k] + (uint32_t)q0 * (uint32_t)d[k];
+    sched_fence();
+}
+
+// Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 ->
+// V mod 2^32: t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t
+// exactly (|v0 + q0 t| < q0 + q0 q1 / 2 and V is the only value of that size
+// in its class); ACC[h][t + 32 brv5(r)] += V.  Eight registers at a time, in
+// phases.
+__device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
+                                             const int32_t (&x1)[32], int lane) {
     mq::static_for<0, 4>([&](auto C_) {
         constexpr int c = decltype(C_)::value;
-        int32_t d[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) d[k] = x1[8 * c + k] - x0[8 * c + k];
-        sched_fence();
-        int64_t p[8];
-        int32_t m[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) p[k] = (int64_t)d[k] * cq;
-        sched_fence();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<1>::qinv);
-        sched_fence();
-        uint32_t old[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * c + k)];
+        int32_t a0[8], a1[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            int32_t tq = (int32_t)((p[k] - (int64_t)m[k] * q1) >> 32);
-            tq += tq < -(q1 / 2) ? q1 : 0;
-            tq -= tq > q1 / 2 ? q1 : 0;
-            d[k] = tq;
+            a0[k] = x0[8 * c + k];
+            a1[k] = x1[8 * c + k];
         }
-        sched_fence();
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            mine[32 * brv5(8 * c + k)] = old[k] + (uint32_t)x0[8 * c + k] + (uint32_t)q0 * (uint32_t)d[k];
-        sched_fence();
+        crt_chunk_q<c>(acc, a0, a1, lane);
     });
 }
 
@@ -997,23 +1011,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             for (int q = 0; q < 32; ++q) S.part[wave - 2][q][lane] = x[q];
         }
         __syncthreads();  // pass-1 sums written; all waves done reading ACC
-        if (wave == 0) {
+        if (wave < 2) {  // wave p: prime p's column sums, inverse transform
 #pragma unroll
-            for (int q = 0; q < 32; ++q) x[q] += S.part[0][q][lane];
-            ntt1024_inv_q<0>(x, tile, twi, t);
-        } else if (wave == 1) {
+            for (int q = 0; q < 32; ++q) x[q] += S.part[wave][q][lane];
+            if (wave == 0)
+                ntt1024_inv_q<0>(x, tile, twi, t);
+            else
+                ntt1024_inv_q<1>(x, tile, twi + 1024, t);
+            // residues of the registers the other waves recombine (this wave
+            // read its part[] slot above)
 #pragma unroll
-            for (int q = 0; q < 32; ++q) x[q] += S.part[1][q][lane];
-            ntt1024_inv_q<1>(x, tile, twi + 1024, t);
-#pragma unroll
-            for (int r = 0; r < 32; ++r) S.part[1][r][lane] = x[r];  // (this wave read part[1] above)
+            for (int r = 0; r < 32; ++r)
+                if (r / 8 != wave) S.part[wave][r][lane] = x[r];
         }
-        __syncthreads();  // prime-1 residues written
-        if (wave == 0) {
-            int32_t x1[32];
+        __syncthreads();  // residues written
+        {  // wave w recombines registers 8w..8w+7
+            int32_t a0[8], a1[8];
 #pragma unroll
-            for (int r = 0; r < 32; ++r) x1[r] = S.part[1][r][lane];
-            crt_update_q(S.acc, x, x1, lane);
+            for (int k = 0; k < 8; ++k) {
+                a0[k] = wave == 0 ? x[k] : S.part[0][8 * wave + k][lane];
+                a1[k] = wave == 1 ? x[8 + k] : S.part[1][8 * wave + k][lane];
+            }
+            switch (wave) {
+            case 0: crt_chunk_q<0>(S.acc, a0, a1, lane); break;
+            case 1: crt_chunk_q<1>(S.acc, a0, a1, lane); break;
+            case 2: crt_chunk_q<2>(S.acc, a0, a1, lane); break;
+            default: crt_chunk_q<3>(S.acc, a0, a1, lane); break;
+            }
         }
         __syncthreads();  // ACC updated
         bk += 2 * 32 * 2 * 64;
