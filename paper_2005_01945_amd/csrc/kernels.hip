@@ -900,8 +900,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if constexpr (A == 1) {
         // Two-prime form: each wave also takes one prime's inverse.  The
         // waves swap the other prime's partial column sums, wave w
-        // finishes prime w, wave 1 hands its residues to wave 0, and wave 0
-        // recombines and updates ACC.
+        // finishes prime w, the waves swap the residues of half of the
+        // registers, and wave w recombines and updates registers 16w..16w+15.
         int32_t* part0 = reinterpret_cast<int32_t*>(&S.part[0][0]);  // [32][64]
         int32_t* part1 = part0 + 32 * 64;
         const int32_t* twi = reinterpret_cast<const int32_t*>(S.twi);
@@ -928,15 +928,44 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
                 for (int q = 0; q < 32; ++q) x[q] = hi_of(mac[q]) + part1[q * 64 + lane];
                 ntt1024_inv_q<1>(x, S.tile[1][h], twi + 1024, t);
-#pragma unroll
-                for (int r = 0; r < 32; ++r) part1[r * 64 + lane] = x[r];
             }
-            __syncthreads();  // prime-1 residues written
-            if (wave == 0) {
-                int32_t x1[32];
+            // wave 0 hands over prime-0 residues of registers 16..31, wave 1
+            // prime-1 residues of registers 0..15 (each read its slot above)
+            {
+                int32_t* mine = wave == 0 ? part0 : part1;
+                const int r0 = wave == 0 ? 16 : 0;
 #pragma unroll
-                for (int r = 0; r < 32; ++r) x1[r] = part1[r * 64 + lane];
-                crt_update_q(S.acc, x, x1, lane);
+                for (int r = 0; r < 16; ++r) mine[(r0 + r) * 64 + lane] = x[r0 + r];
+            }
+            __syncthreads();  // residues written
+            if (wave == 0) {
+                int32_t a0[8], a1[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a0[k] = x[k];
+                    a1[k] = part1[k * 64 + lane];
+                }
+                crt_chunk_q<0>(S.acc, a0, a1, lane);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a0[k] = x[8 + k];
+                    a1[k] = part1[(8 + k) * 64 + lane];
+                }
+                crt_chunk_q<1>(S.acc, a0, a1, lane);
+            } else {
+                int32_t a0[8], a1[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a0[k] = part0[(16 + k) * 64 + lane];
+                    a1[k] = x[16 + k];
+                }
+                crt_chunk_q<2>(S.acc, a0, a1, lane);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a0[k] = part0[(24 + k) * 64 + lane];
+                    a1[k] = x[24 + k];
+                }
+                crt_chunk_q<3>(S.acc, a0, a1, lane);
             }
             __syncthreads();  // ACC updated
             bk += 2 * 32 * 2 * 64;
