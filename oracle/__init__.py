@@ -81,6 +81,8 @@ def lib():
             "or_circuit_add": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_mul": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_mul_tree": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_karatsuba": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_gate_count": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32]),
         }
@@ -240,6 +242,14 @@ class Keys:
         lib().or_circuit_mul_tree(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
+    def karatsuba(self, A, B, width: int, threads: int = 0) -> np.ndarray:
+        """Full 2 width-bit product by Karatsuba's algorithm (Sec. III-B-2)."""
+        a = _c(A, np.uint32).reshape(-1, width, self.width)
+        b = _c(B, np.uint32).reshape(-1, width, self.width)
+        out = np.empty((a.shape[0], 2 * width, self.width), np.uint32)
+        lib().or_circuit_karatsuba(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
     def matvec(self, M, x, rows: int, cols: int, width: int, threads: int = 0) -> np.ndarray:
         m = _c(M, np.uint32).reshape(rows, cols, width, self.width)
         v = _c(x, np.uint32).reshape(cols, width, self.width)
@@ -296,5 +306,17 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3}[kind]
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)
+
+
+def circuit_eval_plain(kind: str, width: int, operand_bits, rows: int = 0, cols: int = 0) -> np.ndarray:
+    """A circuit's gates evaluated on plaintext bits (uint8 0/1, operands LSB
+    first, A then B or M then x); returns the result bits."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
+    bits = _c(operand_bits, np.uint8)
+    nout = rows * width if kind == "matvec" else (2 * width if kind == "karatsuba" else width)
+    out = np.empty(nout, np.uint8)
+    got = lib().or_circuit_eval_plain(k, width, rows, cols, _u8p(bits), _u8p(out))
+    assert got == nout
+    return out

@@ -10,6 +10,7 @@
 
 #include <math.h>
 #include <pthread.h>
+#include <assert.h>
 #include <stdlib.h>
 #include <string.h>
 #include <unistd.h>
@@ -568,6 +569,163 @@ static void build_mul_tree(or_prog* pr, const long* a, const long* b, int w, lon
     free(sum);
 }
 
+/* ---- Karatsuba multiplication (Sec. III-B-2, Algorithm 1; Sec. V-B-2) ----
+ * Full products (2n bits of n-bit operands).  Numbers are wire arrays, LSB
+ * first; a bit beyond an array's length is zero and carries no wire. */
+
+/* r = x + y mod 2^L (r has L wires; lx, ly <= L).  Ripple carry: both bits
+ * present and no carry in: r = x^y, c = x&y; with a carry in:
+ * t = x^y, r = t^c, c = (x&y) | (t&c); one bit and a carry: r = v^c,
+ * c = v&c; one bit alone: r = that wire; no bit: r = the carry (then no
+ * higher bit exists).  Carries only where a higher bit needs them.
+ * Returns the number of wires written (L, or fewer when the sum is shorter). */
+static int build_add_n(or_prog* pr, const long* x, int lx, const long* y, int ly, int L, long* r) {
+    long c = -1;
+    int n = 0;
+    for (int i = 0; i < L; i++) {
+        const int hx = i < lx, hy = i < ly, more = i + 1 < L;
+        long nc = -1;
+        if (hx && hy) {
+            if (c < 0) {
+                r[n++] = emit(pr, OR_XOR, x[i], y[i]);
+                if (more) nc = emit(pr, OR_AND, x[i], y[i]);
+            } else {
+                long t = emit(pr, OR_XOR, x[i], y[i]);
+                r[n++] = emit(pr, OR_XOR, t, c);
+                if (more) {
+                    long g = emit(pr, OR_AND, x[i], y[i]);
+                    long h = emit(pr, OR_AND, t, c);
+                    nc = emit(pr, OR_OR, g, h);
+                }
+            }
+        } else if (hx || hy) {
+            long v = hx ? x[i] : y[i];
+            if (c < 0) {
+                r[n++] = v;
+            } else {
+                r[n++] = emit(pr, OR_XOR, v, c);
+                if (more) nc = emit(pr, OR_AND, v, c);
+            }
+        } else {
+            if (c < 0) break;
+            r[n++] = c;
+        }
+        c = nc;
+    }
+    return n;
+}
+
+/* r = x - y mod 2^L (both L bits) as x + ~y + 1 with the +1 folded into
+ * bit 0: r_0 = x^y, c = x | ~y (ORYN); bit i: t = x XNOR y, r = t^c,
+ * c = (x & ~y) | (t & c) (ANDYN, AND, OR). */
+static void build_sub_n(or_prog* pr, const long* x, const long* y, int L, long* r) {
+    long c = -1;
+    for (int i = 0; i < L; i++) {
+        const int more = i + 1 < L;
+        if (i == 0) {
+            r[0] = emit(pr, OR_XOR, x[0], y[0]);
+            if (more) c = emit(pr, OR_ORYN, x[0], y[0]);
+            continue;
+        }
+        long t = emit(pr, OR_XNOR, x[i], y[i]);
+        r[i] = emit(pr, OR_XOR, t, c);
+        if (more) {
+            long g = emit(pr, OR_ANDYN, x[i], y[i]);
+            long h = emit(pr, OR_AND, t, c);
+            c = emit(pr, OR_OR, g, h);
+        }
+    }
+}
+
+/* Full product of m-bit a and b (2m wires into r, m >= 2) with the partial
+ * products (A & b_i) << i summed by the tree of Sec. V-B-2: first and second
+ * halves of the list added element-wise, an odd last element waiting a
+ * round; a sum keeps one bit more than its wider operand, up to 2m. */
+static void build_mul_full_tree(or_prog* pr, const long* a, const long* b, int m, long* r) {
+    const int W2 = 2 * m;
+    long* bits = (long*)malloc((size_t)m * W2 * sizeof(long)); /* number k: wires of bits low[k].. */
+    int* low = (int*)malloc((size_t)m * sizeof(int));
+    int* len = (int*)malloc((size_t)m * sizeof(int));
+    long* sum = (long*)malloc((size_t)W2 * sizeof(long));
+    for (int i = 0; i < m; i++) {
+        low[i] = i;
+        len[i] = m;
+        for (int j = 0; j < m; j++) bits[(size_t)i * W2 + j] = emit(pr, OR_AND, a[j], b[i]);
+    }
+    int cnt = m;
+    while (cnt > 1) {
+        int h = cnt / 2;
+        for (int k = 0; k < h; k++) {
+            int ix = k, iy = k + h;
+            if (low[iy] < low[ix]) { int u = ix; ix = iy; iy = u; }
+            const long* x = bits + (size_t)ix * W2;
+            const long* y = bits + (size_t)iy * W2;
+            const int skip = low[iy] - low[ix];
+            int top = low[ix] + len[ix];
+            if (low[iy] + len[iy] > top) top = low[iy] + len[iy];
+            const int L = (top + 1 < W2 ? top + 1 : W2) - low[iy];
+            assert(len[ix] >= skip); /* no gap between the two numbers' wired bits */
+            const int lxh = len[ix] - skip;
+            const int ns = build_add_n(pr, x + skip, lxh, y, len[iy], L, sum);
+            long* dst = bits + (size_t)k * W2;
+            const int nl = low[ix];
+            memmove(dst, x, (size_t)skip * sizeof(long)); /* x's own low bits (skip <= len[ix]) */
+            memcpy(dst + skip, sum, (size_t)ns * sizeof(long));
+            low[k] = nl;
+            len[k] = skip + ns;
+        }
+        if (cnt & 1) {
+            memcpy(bits + (size_t)h * W2, bits + (size_t)(cnt - 1) * W2, (size_t)W2 * sizeof(long));
+            low[h] = low[cnt - 1];
+            len[h] = len[cnt - 1];
+        }
+        cnt = h + (cnt & 1);
+    }
+    assert(low[0] == 0 && len[0] == W2); /* one number left, at offset 0, 2m bits long */
+    memcpy(r, bits, (size_t)W2 * sizeof(long));
+    free(bits);
+    free(low);
+    free(len);
+    free(sum);
+}
+
+#define OR_KARATSUBA_BASE 16 /* operands narrower than this: tree base multiplier */
+
+/* Algorithm 1 (Sec. III-B-2) with n-bit operands, r = 2n wires: n < 16:
+ * base product; else with h = floor(n/2), X = X0 + 2^h X1 (Y likewise):
+ * Z0 = X0 Y0, Z1 = X1 Y1, Z2 = (X0 + X1)(Y0 + Y1) (operands n - h + 1 bits),
+ * M = Z2 - Z1 - Z0 = X0 Y1 + X1 Y0 (computed mod 2^(n+1), where it fits),
+ * Z = Z0 + 2^h M + 2^(2h) Z1: Z0 and 2^(2h) Z1 do not overlap, so M is added
+ * to their concatenation from bit h on. */
+static void build_karatsuba(or_prog* pr, const long* X, const long* Y, int n, long* r) {
+    if (n < OR_KARATSUBA_BASE) {
+        build_mul_full_tree(pr, X, Y, n, r);
+        return;
+    }
+    const int h = n / 2, u = n - h, s = u + 1;
+    long* S = (long*)malloc((size_t)s * sizeof(long));
+    long* T = (long*)malloc((size_t)s * sizeof(long));
+    long* Z2 = (long*)malloc((size_t)2 * s * sizeof(long));
+    long* P = (long*)malloc((size_t)(n + 1) * sizeof(long));
+    long* M = (long*)malloc((size_t)(n + 1) * sizeof(long));
+    long* hi = (long*)malloc((size_t)2 * n * sizeof(long));
+    build_karatsuba(pr, X, Y, h, r);                /* Z0 -> r[0, 2h) */
+    build_karatsuba(pr, X + h, Y + h, u, r + 2 * h); /* Z1 -> r[2h, 2n) */
+    build_add_n(pr, X, h, X + h, u, s, S);
+    build_add_n(pr, Y, h, Y + h, u, s, T);
+    build_karatsuba(pr, S, T, s, Z2);
+    build_add_n(pr, r, 2 * h, r + 2 * h, 2 * u, n + 1, P);
+    build_sub_n(pr, Z2, P, n + 1, M);
+    build_add_n(pr, r + h, 2 * n - h, M, n + 1, 2 * n - h, hi);
+    memcpy(r + h, hi, (size_t)(2 * n - h) * sizeof(long));
+    free(S);
+    free(T);
+    free(Z2);
+    free(P);
+    free(M);
+    free(hi);
+}
+
 /* Tree accumulation (Sec. V-B-2, Fig. 4): the list is split into its first
  * and second halves, which are added element-wise; an odd last element is
  * carried to the next round unchanged. */
@@ -623,14 +781,15 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     free(o);
 }
 
-enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3 };
+enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
     const size_t W = (size_t)K->P.n + 1;
     or_prog pr = {0};
     pr.nwires = (long)(2 * count * (size_t)width);
-    long* outw = (long*)malloc(count * (size_t)width * sizeof(long));
+    const int32_t ow = kind == KIND_KARATSUBA ? 2 * width : width; /* result bits */
+    long* outw = (long*)malloc(count * (size_t)ow * sizeof(long));
     long* ia = (long*)malloc((size_t)width * sizeof(long));
     long* ib = (long*)malloc((size_t)width * sizeof(long));
     for (size_t c = 0; c < count; c++) {
@@ -638,15 +797,16 @@ static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const 
             ia[k] = (long)(c * width + k);
             ib[k] = (long)((count + c) * width + k);
         }
-        if (kind == KIND_ADD) build_add(&pr, ia, ib, width, outw + c * width);
-        else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, outw + c * width);
-        else build_mul(&pr, ia, ib, width, outw + c * width);
+        if (kind == KIND_ADD) build_add(&pr, ia, ib, width, outw + c * ow);
+        else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, outw + c * ow);
+        else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, outw + c * ow);
+        else build_mul(&pr, ia, ib, width, outw + c * ow);
     }
     uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
     memcpy(wires, A, count * width * W * sizeof(uint32_t));
     memcpy(wires + count * width * W, B, count * width * W * sizeof(uint32_t));
     run_prog(K, &pr, wires, threads);
-    for (size_t q = 0; q < count * (size_t)width; q++)
+    for (size_t q = 0; q < count * (size_t)ow; q++)
         memcpy(R + q * W, wires + (size_t)outw[q] * W, W * sizeof(uint32_t));
     free(wires);
     free(outw);
@@ -668,6 +828,11 @@ void or_circuit_mul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint
 void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                          size_t count, int32_t width, int threads) {
     circuit_binary(K, KIND_MUL_TREE, A, B, R, count, width, threads);
+}
+
+void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                          size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_KARATSUBA, A, B, R, count, width, threads);
 }
 
 /* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the shift-and-add multiplier,
@@ -707,6 +872,65 @@ void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, u
     free(pr.g);
 }
 
+/* Truth table of gate op on plaintext bits (the readings of the gate list). */
+static int plain_gate(int op, int a, int b) {
+    switch (op) {
+    case OR_AND: return a & b;
+    case OR_NAND: return !(a & b);
+    case OR_OR: return a | b;
+    case OR_NOR: return !(a | b);
+    case OR_XOR: return a ^ b;
+    case OR_XNOR: return !(a ^ b);
+    case OR_ANDNY: return (!a) & b;
+    case OR_ANDYN: return a & !b;
+    case OR_ORNY: return (!a) | b;
+    case OR_ORYN: return a | !b;
+    default: return -1;
+    }
+}
+
+/* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba} (kind 0..4)
+ * evaluated on plaintext bits, gate by gate in the order the program lists
+ * them: in = operand bits (A then B, or M then x), LSB first, one byte per
+ * bit; out = result bits.  Returns the number of result bits. */
+long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out) {
+    or_prog pr = {0};
+    long nin, nout;
+    long* res;
+    if (kind == KIND_MATVEC) {
+        nin = (long)rows * cols * width + (long)cols * width;
+        nout = (long)rows * width;
+        pr.nwires = nin;
+        res = (long*)malloc((size_t)nout * sizeof(long));
+        build_matvec(&pr, rows, cols, width, res);
+    } else {
+        nin = 2L * width;
+        nout = kind == KIND_KARATSUBA ? 2L * width : width;
+        pr.nwires = nin;
+        long* ia = (long*)malloc((size_t)width * sizeof(long));
+        long* ib = (long*)malloc((size_t)width * sizeof(long));
+        res = (long*)malloc((size_t)nout * sizeof(long));
+        for (int32_t k = 0; k < width; k++) { ia[k] = k; ib[k] = width + k; }
+        if (kind == KIND_ADD) build_add(&pr, ia, ib, width, res);
+        else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, res);
+        else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, res);
+        else build_mul(&pr, ia, ib, width, res);
+        free(ia);
+        free(ib);
+    }
+    uint8_t* v = (uint8_t*)malloc((size_t)pr.nwires);
+    memcpy(v, in, (size_t)nin);
+    for (long k = 0; k < pr.ng; k++) {
+        const or_gate_t* G = &pr.g[k];
+        v[G->out] = (uint8_t)plain_gate(G->op, v[G->in0], v[G->in1]);
+    }
+    for (long q = 0; q < nout; q++) out[q] = v[res[q]];
+    free(v);
+    free(res);
+    free(pr.g);
+    return nout;
+}
+
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) {
     or_prog pr = {0};
     long n;
@@ -718,11 +942,12 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
     } else {
         long* ia = (long*)malloc((size_t)width * sizeof(long));
         long* ib = (long*)malloc((size_t)width * sizeof(long));
-        long* r = (long*)malloc((size_t)width * sizeof(long));
+        long* r = (long*)malloc((size_t)2 * width * sizeof(long));
         for (int32_t k = 0; k < width; k++) { ia[k] = k; ib[k] = width + k; }
         pr.nwires = 2L * width;
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, r);
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, r);
+        else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, r);
         else build_mul(&pr, ia, ib, width, r);
         free(ia);
         free(ib);

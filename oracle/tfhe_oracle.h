@@ -112,10 +112,18 @@ void or_circuit_mul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint
  * (Sec. V-B-2): same gates as or_circuit_mul, fewer levels. */
 void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                          size_t count, int32_t width, int threads);
+/* Full product (2 width bits into R, [count][2 width][n+1]) by Karatsuba's
+ * algorithm (Sec. III-B-2, Algorithm 1), operands below 16 bits by the
+ * tree-accumulated base product. */
+void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                          size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
+/* The same circuits evaluated on plaintext bits (one byte per bit, operands
+ * LSB first); returns the number of result bits written to out. */
+long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out);
 /* Number of bootstrapped gates the circuits above evaluate (no evaluation);
- * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation. */
+ * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba. */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

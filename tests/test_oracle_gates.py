@@ -151,6 +151,17 @@ def test_mul_tree_circuit_decrypts_to_low_product(okeys):
     np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a * b) % (1 << w))
 
 
+def test_karatsuba_circuit_decrypts_to_full_product(okeys):
+    """Karatsuba's algorithm returns all 2w bits of the product (below 16 bits
+    through its base product)."""
+    w = 4
+    a = np.array([13], np.uint64)
+    b = np.array([11], np.uint64)
+    R = okeys.karatsuba(okeys.encrypt_uint(a, w, nonce=74_000), okeys.encrypt_uint(b, w, nonce=84_000), w)
+    assert R.shape[1] == 2 * w
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, 2 * w), a * b)
+
+
 def test_matvec_circuit_decrypts_to_product(okeys):
     w, rows, cols = 2, 2, 2
     M = np.array([[3, 2], [1, 3]], np.uint64)
