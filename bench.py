@@ -340,7 +340,7 @@ def main():
 
     # latency of one 32-bit multiplication: shift-and-add (120 levels) and with
     # the partial products summed by a tree (62 levels), same 2,824 gates
-    mul = mul_tree = None
+    mul = mul_tree = mul_kara = None
     if args.mul_samples > 0:
         ma = workloads.uniform_uints(11, 1, 32)
         mb = workloads.uniform_uints(12, 1, 32)
@@ -367,6 +367,21 @@ def main():
         log(f"mul32 latency: {mul}")
         mul_tree = mul_latency(F.fhe_mul_tree, "mul_tree")
         log(f"mul32 (tree accumulation) latency: {mul_tree}")
+        # Karatsuba (Sec. III-B-2): all 64 bits of the product
+        mR2 = torch.empty((1, 64, mA.shape[-1]), dtype=mA.dtype, device=mA.device)
+        F.fhe_mul_karatsuba(ctx, mA, mB, mR2, 1, 32, stream)
+        torch.cuda.synchronize()
+        kl = []
+        for _ in range(args.mul_samples):
+            s0 = time.perf_counter()
+            F.fhe_mul_karatsuba(ctx, mA, mB, mR2, 1, 32, stream)
+            torch.cuda.synchronize()
+            kl.append(time.perf_counter() - s0)
+        assert sk.decrypt_uint(F.to_host(mR2), 64)[0] == int(ma[0]) * int(mb[0])
+        kg, klv, _ = F.fhe_circuit_shape("karatsuba", 32)
+        mul_kara = {"p50_ms": round(1e3 * float(np.median(kl)), 1), "p99_ms": round(1e3 * float(np.percentile(kl, 99)), 1),
+                    "samples": len(kl), "gates": kg, "levels": klv, "product_bits": 64}
+        log(f"mul32 Karatsuba (64-bit product) latency: {mul_kara}")
 
     serving = None
     if args.serve_jobs > 0:
@@ -389,7 +404,8 @@ def main():
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": workload,
-        "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree, "serving": serving,
+        "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
+        "mul32_karatsuba_latency": mul_kara, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": per_shape},

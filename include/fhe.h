@@ -198,6 +198,16 @@ int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, siz
 int fhe_mul_tree(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
                  uint32_t width, void* stream);
 
+/* R = A * B in full (2 width bits: R is [count][2 width][n+1]) by Karatsuba's
+ * algorithm (Sec. III-B-2, Algorithm 1): from 16-bit operands on, three
+ * half-width products Z0 = X0 Y0, Z1 = X1 Y1, Z2 = (X0 + X1)(Y0 + Y1) and
+ * Z = Z0 + (Z2 - Z1 - Z0) 2^h + Z1 2^(2h), h = floor(width / 2), the
+ * subtraction as an addition of the complement; narrower operands by the
+ * tree-accumulated product.  5,271 gates in 116 levels at width 32.
+ * EINVAL: width outside 2..64, null buffers. */
+int fhe_mul_karatsuba(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                      uint32_t width, void* stream);
+
 /* y = M x mod 2^width: every product by the shift-and-add multiplier, each row summed
  * by a tree of adders (Sec. V-B-2, Fig. 4: split in halves, add pairwise).
  * M: device uint32[rows][cols][width][n+1]; x: [cols][width][n+1];
@@ -253,8 +263,8 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
                               const fhe_launch_config* cfg);
 
 /* Number of gates and of levels of a circuit as the library schedules it
- * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation;
- * rows/cols only for matvec). */
+ * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation,
+ * 4 = Karatsuba; rows/cols only for matvec). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 

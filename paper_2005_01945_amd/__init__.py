@@ -67,6 +67,7 @@ _SIGS = {
     "fhe_add": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul_tree": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
@@ -284,14 +285,20 @@ def fhe_mul_tree(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_mul_tree(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_mul_tree")
 
 
+def fhe_mul_karatsuba(ctx, A, B, R, count, width, stream=None):
+    """R ([count][2 width][n+1]) = full products A * B by Karatsuba's algorithm."""
+    _check(lib().fhe_mul_karatsuba(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)),
+           "fhe_mul_karatsuba")
+
+
 def fhe_matvec(ctx, M, x, y, rows, cols, width, stream=None):
     _check(lib().fhe_matvec(ctx.h, _dev(M), _dev(x), _dev(y), rows, cols, width, _stream(stream)),
            "fhe_matvec")
 
 
 def fhe_circuit_shape(kind, width, rows=0, cols=0):
-    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree'}."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3}[kind]
+    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree', 'karatsuba'}."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
     g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")

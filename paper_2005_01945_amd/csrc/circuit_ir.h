@@ -7,7 +7,7 @@
 
 namespace fhe {
 
-enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3 };
+enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3, kKaratsuba = 4 };
 
 struct Gate {
     uint8_t op;
@@ -24,8 +24,9 @@ struct Circuit {
     uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
 };
 
-// kind: kAdd / kMul / kMulTree (operands of width w) or kMatvec (rows x cols
-// matrix of w-bit entries times a cols-vector).
+// kind: kAdd / kMul / kMulTree / kKaratsuba (operands of width w; Karatsuba
+// has 2w result bits) or kMatvec (rows x cols matrix of w-bit entries times a
+// cols-vector).
 Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols);
 
 // ASAP level of every gate (inputs are level 0); *depth = deepest level.

@@ -15,6 +15,12 @@
 //    Adding numbers whose known-zero low bits end at l < m copies bits
 //    l..m-1 of the first and ripple-adds bits m..w-1.  Same gates as mul,
 //    depth 62 instead of 120 at w = 32.
+//  - Karatsuba (Sec. III-B-2, Algorithm 1), full 2w-bit product: below 16
+//    bits the tree-accumulated full product (a sum keeps one bit more than
+//    its wider operand, up to 2w); else with h = floor(w/2), Z0 = X0 Y0,
+//    Z1 = X1 Y1, Z2 = (X0 + X1)(Y0 + Y1), M = Z2 - (Z0 + Z1) mod 2^(w+1)
+//    (subtraction as x + ~y + 1: XNOR / ANDYN gates, the +1 folded into bit
+//    0 as XOR / ORYN), Z = (Z0 | Z1 << 2h) + M << h.
 //  - matvec: every product by mul; each row's products accumulated by the
 //    tree of Sec. V-B-2 / Fig. 4: the list is split into first and second
 //    halves that are added element-wise, an odd last element waits a round.
@@ -38,6 +44,8 @@
 namespace fhe {
 
 namespace {
+
+constexpr size_t kKaratsubaBase = 16;  // narrower operands: base product
 
 class Builder {
   public:
@@ -114,6 +122,120 @@ class Builder {
         }
         return parts.empty() ? std::vector<uint32_t>() : parts[0].bits;
     }
+    // x + y mod 2^len; missing high bits are zero.  The result can be
+    // shorter than len when its top bits are known zero.
+    std::vector<uint32_t> add_to(const std::vector<uint32_t>& x, const std::vector<uint32_t>& y, size_t len) {
+        std::vector<uint32_t> r;
+        bool have_c = false;
+        uint32_t c = 0;
+        for (size_t i = 0; i < len; ++i) {
+            const bool hx = i < x.size(), hy = i < y.size(), more = i + 1 < len;
+            bool next_c = false;
+            uint32_t nc = 0;
+            if (hx && hy) {
+                const uint32_t t = gate(FHE_XOR, x[i], y[i]);
+                if (!have_c) {
+                    r.push_back(t);
+                    if (more) { nc = gate(FHE_AND, x[i], y[i]); next_c = true; }
+                } else {
+                    r.push_back(gate(FHE_XOR, t, c));
+                    if (more) {
+                        const uint32_t g = gate(FHE_AND, x[i], y[i]);
+                        const uint32_t h = gate(FHE_AND, t, c);
+                        nc = gate(FHE_OR, g, h);
+                        next_c = true;
+                    }
+                }
+            } else if (hx || hy) {
+                const uint32_t v = hx ? x[i] : y[i];
+                if (!have_c) {
+                    r.push_back(v);
+                } else {
+                    r.push_back(gate(FHE_XOR, v, c));
+                    if (more) { nc = gate(FHE_AND, v, c); next_c = true; }
+                }
+            } else {
+                if (!have_c) break;
+                r.push_back(c);
+            }
+            have_c = next_c;
+            c = nc;
+        }
+        return r;
+    }
+    // x - y mod 2^len (both len bits) as x + ~y + 1.
+    std::vector<uint32_t> sub_to(const std::vector<uint32_t>& x, const std::vector<uint32_t>& y, size_t len) {
+        std::vector<uint32_t> r(len);
+        uint32_t c = 0;
+        for (size_t i = 0; i < len; ++i) {
+            const bool more = i + 1 < len;
+            if (i == 0) {
+                r[0] = gate(FHE_XOR, x[0], y[0]);
+                if (more) c = gate(FHE_ORYN, x[0], y[0]);
+                continue;
+            }
+            const uint32_t t = gate(FHE_XNOR, x[i], y[i]);
+            r[i] = gate(FHE_XOR, t, c);
+            if (more) {
+                const uint32_t g = gate(FHE_ANDYN, x[i], y[i]);
+                const uint32_t h = gate(FHE_AND, t, c);
+                c = gate(FHE_OR, g, h);
+            }
+        }
+        return r;
+    }
+    // Full 2m-bit product, partial products summed by the first/second-half
+    // tree.
+    std::vector<uint32_t> mul_full_tree(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t m = a.size(), top_bits = 2 * m;
+        struct Num {
+            size_t low;
+            std::vector<uint32_t> bits;
+        };
+        std::vector<Num> nums;
+        for (size_t i = 0; i < m; ++i) {
+            Num v{i, std::vector<uint32_t>(m)};
+            for (size_t j = 0; j < m; ++j) v.bits[j] = gate(FHE_AND, a[j], b[i]);
+            nums.push_back(std::move(v));
+        }
+        while (nums.size() > 1) {
+            const size_t h = nums.size() / 2;
+            std::vector<Num> next;
+            for (size_t k = 0; k < h; ++k) {
+                const Num* x = &nums[k];
+                const Num* y = &nums[k + h];
+                if (y->low < x->low) std::swap(x, y);
+                const size_t skip = y->low - x->low;
+                const size_t top = std::max(x->low + x->bits.size(), y->low + y->bits.size());
+                const size_t len = std::min(top + 1, top_bits) - y->low;
+                const std::vector<uint32_t> hi(x->bits.begin() + skip, x->bits.end());
+                const std::vector<uint32_t> s = add_to(hi, y->bits, len);
+                Num z{x->low, std::vector<uint32_t>(x->bits.begin(), x->bits.begin() + skip)};
+                z.bits.insert(z.bits.end(), s.begin(), s.end());
+                next.push_back(std::move(z));
+            }
+            if (nums.size() & 1) next.push_back(std::move(nums.back()));
+            nums.swap(next);
+        }
+        return nums[0].bits;  // offset 0, 2m bits
+    }
+    std::vector<uint32_t> karatsuba(const std::vector<uint32_t>& x, const std::vector<uint32_t>& y) {
+        const size_t n = x.size();
+        if (n < kKaratsubaBase) return mul_full_tree(x, y);
+        const size_t h = n / 2, u = n - h;
+        const std::vector<uint32_t> x0(x.begin(), x.begin() + h), x1(x.begin() + h, x.end());
+        const std::vector<uint32_t> y0(y.begin(), y.begin() + h), y1(y.begin() + h, y.end());
+        const std::vector<uint32_t> z0 = karatsuba(x0, y0);  // 2h bits
+        const std::vector<uint32_t> z1 = karatsuba(x1, y1);  // 2u bits
+        const std::vector<uint32_t> z2 = karatsuba(add_to(x0, x1, u + 1), add_to(y0, y1, u + 1));
+        const std::vector<uint32_t> p = add_to(z0, z1, n + 1);
+        const std::vector<uint32_t> m = sub_to(std::vector<uint32_t>(z2.begin(), z2.begin() + n + 1), p, n + 1);
+        std::vector<uint32_t> z(z0);
+        z.insert(z.end(), z1.begin(), z1.end());  // Z0 | Z1 << 2h
+        const std::vector<uint32_t> hi = add_to(std::vector<uint32_t>(z.begin() + h, z.end()), m, 2 * n - h);
+        std::copy(hi.begin(), hi.end(), z.begin() + h);
+        return z;
+    }
     std::vector<uint32_t> tree_sum(std::vector<std::vector<uint32_t>> vals) {
         while (vals.size() > 1) {
             const size_t h = vals.size() / 2;
@@ -148,7 +270,10 @@ Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
     }
     Builder B(w, w);
     const std::vector<uint32_t> a = iota_wires(0, w), b = iota_wires(w, w);
-    B.c.outputs = kind == kAdd ? B.add(a, b) : kind == kMulTree ? B.mul_tree(a, b) : B.mul(a, b);
+    B.c.outputs = kind == kAdd        ? B.add(a, b)
+                  : kind == kMulTree  ? B.mul_tree(a, b)
+                  : kind == kKaratsuba ? B.karatsuba(a, b)
+                                       : B.mul(a, b);
     return B.c;
 }
 
@@ -385,6 +510,12 @@ extern "C" int fhe_mul_tree(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, 
     return run_circuit(ctx, kMulTree, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul_tree");
 }
 
+extern "C" int fhe_mul_karatsuba(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                                 uint32_t width, void* stream) {
+    if (width < 2) return set_error(FHE_EINVAL, "fhe_mul_karatsuba: width %u below 2", width);
+    return run_circuit(ctx, kKaratsuba, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul_karatsuba");
+}
+
 extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
                           uint32_t cols, uint32_t width, void* stream) {
     if (rows == 0 || cols == 0) return set_error(FHE_EINVAL, "fhe_matvec: empty matrix");
@@ -393,7 +524,7 @@ extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, ui
 
 extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,
                                  uint32_t* levels, uint64_t* widest_level) {
-    if (kind < 0 || kind > 3 || width < 1 || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
+    if (kind < 0 || kind > 4 || width < 1 || (kind == kKaratsuba && width < 2) || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
         return set_error(FHE_EINVAL, "fhe_circuit_shape: bad arguments");
     const Circuit c = build_circuit(kind, width, rows, cols);
     uint32_t depth = 0;

@@ -128,6 +128,44 @@ def test_mul_tree32_decrypts_and_mul_tree16_bit_exact(env):
     np.testing.assert_array_equal(got16, K.mul_tree(c16a, c16b, 16))
 
 
+@pytest.mark.parametrize("width,count", [(4, 3), (16, 1)])
+def test_karatsuba_bit_exact(env, width, count):
+    """Full products by Karatsuba's algorithm (Sec. III-B-2): through the base
+    product at 4 bits, one level of the recursion at 16 bits (1,457 gates)."""
+    import torch
+    sk, ctx, K = env
+    a = workloads.uniform_uints(90 + width, count, width)
+    b = workloads.uniform_uints(95 + width, count, width)
+    ca = sk.encrypt_uint(a, width, nonce=1_300_000)
+    cb = sk.encrypt_uint(b, width, nonce=1_400_000)
+    dA, dB = F.to_device(ca), F.to_device(cb)
+    dR = torch.empty((count, 2 * width, F.WORDS), dtype=torch.int32, device="cuda")
+    log(f"karatsuba width={width} count={count}")
+    F.fhe_mul_karatsuba(ctx, dA, dB, dR, count, width)
+    torch.cuda.synchronize()
+    got = F.to_host(dR)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, 2 * width).astype(object),
+                                  a.astype(object) * b.astype(object))
+    log(f"oracle: karatsuba width={width}")
+    np.testing.assert_array_equal(got, K.karatsuba(ca, cb, width))
+
+
+def test_karatsuba32_full_products_decrypt(env):
+    """32 pairs of uniform uint32: all 64 bits of every product."""
+    import torch
+    sk, ctx, K = env
+    a = workloads.uniform_uints(96, 32, 32)
+    b = workloads.uniform_uints(97, 32, 32)
+    dA = F.to_device(sk.encrypt_uint(a, 32, nonce=1_500_000))
+    dB = F.to_device(sk.encrypt_uint(b, 32, nonce=1_600_000))
+    dR = torch.empty((32, 64, F.WORDS), dtype=torch.int32, device="cuda")
+    log("karatsuba32 x 32 pairs")
+    F.fhe_mul_karatsuba(ctx, dA, dB, dR, 32, 32)
+    torch.cuda.synchronize()
+    got = sk.decrypt_uint(F.to_host(dR), 64).astype(object)
+    np.testing.assert_array_equal(got, a.astype(object) * b.astype(object))
+
+
 def test_mul32_full_size_decrypts(env):
     """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
     product decrypts correctly."""

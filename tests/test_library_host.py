@@ -120,6 +120,8 @@ def test_circuit_shapes_match_oracle_gate_counts():
         assert F.fhe_circuit_shape("add", w)[0] == oracle.circuit_gate_count("add", w)
         assert F.fhe_circuit_shape("mul", w)[0] == oracle.circuit_gate_count("mul", w)
         assert F.fhe_circuit_shape("mul_tree", w)[0] == oracle.circuit_gate_count("mul_tree", w)
+    for w in (2, 5, 15, 16, 17, 24, 32, 33, 64):
+        assert F.fhe_circuit_shape("karatsuba", w)[0] == oracle.circuit_gate_count("karatsuba", w)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64)[0] == oracle.circuit_gate_count("matvec", 16, 64, 64)
     assert F.fhe_circuit_shape("matvec", 3, 5, 7)[0] == oracle.circuit_gate_count("matvec", 3, 5, 7)
     # gates, ASAP depth, widest level of the paper-sized circuits
@@ -128,4 +130,6 @@ def test_circuit_shapes_match_oracle_gate_counts():
     # tree accumulation: five rounds of additions whose ripple carries overlap
     assert F.fhe_circuit_shape("mul_tree", 32) == (2824, 62, 528)
     assert [F.fhe_circuit_shape("mul_tree", w)[1] for w in (8, 16)] == [14, 30]
+    assert F.fhe_circuit_shape("karatsuba", 32)[:2] == (5271, 116)
+    assert F.fhe_circuit_shape("karatsuba", 16)[:2] == (1457, 58)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64) == (2952576, 68, 557056)
