@@ -82,6 +82,7 @@ def lib():
             "or_circuit_mul": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_mul_tree": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_karatsuba": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_add_numberwise": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_gate_count": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32]),
@@ -242,6 +243,14 @@ class Keys:
         lib().or_circuit_mul_tree(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
+    def add_numberwise(self, A, B, width: int, threads: int = 0) -> np.ndarray:
+        """(A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1)."""
+        a = _c(A, np.uint32).reshape(-1, width, self.width)
+        b = _c(B, np.uint32).reshape(-1, width, self.width)
+        out = np.empty_like(a)
+        lib().or_circuit_add_numberwise(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
     def karatsuba(self, A, B, width: int, threads: int = 0) -> np.ndarray:
         """Full 2 width-bit product by Karatsuba's algorithm (Sec. III-B-2)."""
         a = _c(A, np.uint32).reshape(-1, width, self.width)
@@ -306,14 +315,14 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)
 
 
 def circuit_eval_plain(kind: str, width: int, operand_bits, rows: int = 0, cols: int = 0) -> np.ndarray:
     """A circuit's gates evaluated on plaintext bits (uint8 0/1, operands LSB
     first, A then B or M then x); returns the result bits."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5}[kind]
     bits = _c(operand_bits, np.uint8)
     nout = rows * width if kind == "matvec" else (2 * width if kind == "karatsuba" else width)
     out = np.empty(nout, np.uint8)

@@ -569,6 +569,25 @@ static void build_mul_tree(or_prog* pr, const long* a, const long* b, int w, lon
     free(sum);
 }
 
+/* Number-wise addition (GPU_n, Sec. V-B-1), sum mod 2^w: R = A; then w
+ * rounds of carry = R & B, R = R ^ B, B = carry << 1 (the AND and XOR of a
+ * round side by side).  After round k the low k+1 bits of B are zero and carry
+ * no wire, so round k acts on bits k..w-1 only (its carry out of bit w-1 is
+ * dropped): w^2 gates in w levels. */
+static void build_add_numberwise(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    long* B = (long*)malloc((size_t)w * sizeof(long));
+    long* carry = (long*)malloc((size_t)w * sizeof(long));
+    memcpy(r, a, (size_t)w * sizeof(long));
+    memcpy(B, b, (size_t)w * sizeof(long));
+    for (int k = 0; k < w; k++) {
+        for (int i = k; i + 1 < w; i++) carry[i] = emit(pr, OR_AND, r[i], B[i]);
+        for (int i = k; i < w; i++) r[i] = emit(pr, OR_XOR, r[i], B[i]);
+        for (int i = w - 1; i > k; i--) B[i] = carry[i - 1];
+    }
+    free(B);
+    free(carry);
+}
+
 /* ---- Karatsuba multiplication (Sec. III-B-2, Algorithm 1; Sec. V-B-2) ----
  * Full products (2n bits of n-bit operands).  Numbers are wire arrays, LSB
  * first; a bit beyond an array's length is zero and carries no wire. */
@@ -781,7 +800,7 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     free(o);
 }
 
-enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4 };
+enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4, KIND_ADD_NUMBERWISE = 5 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
@@ -800,6 +819,7 @@ static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const 
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, outw + c * ow);
+        else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, outw + c * ow);
         else build_mul(&pr, ia, ib, width, outw + c * ow);
     }
     uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
@@ -833,6 +853,11 @@ void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B,
 void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                           size_t count, int32_t width, int threads) {
     circuit_binary(K, KIND_KARATSUBA, A, B, R, count, width, threads);
+}
+
+void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                               size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_ADD_NUMBERWISE, A, B, R, count, width, threads);
 }
 
 /* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the shift-and-add multiplier,
@@ -889,7 +914,8 @@ static int plain_gate(int op, int a, int b) {
     }
 }
 
-/* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba} (kind 0..4)
+/* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba,add_numberwise}
+ * (kind 0..5)
  * evaluated on plaintext bits, gate by gate in the order the program lists
  * them: in = operand bits (A then B, or M then x), LSB first, one byte per
  * bit; out = result bits.  Returns the number of result bits. */
@@ -914,6 +940,7 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, res);
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, res);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, res);
+        else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, res);
         else build_mul(&pr, ia, ib, width, res);
         free(ia);
         free(ib);
@@ -948,6 +975,7 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
         if (kind == KIND_ADD) build_add(&pr, ia, ib, width, r);
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, r);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, r);
+        else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, r);
         else build_mul(&pr, ia, ib, width, r);
         free(ia);
         free(ib);

@@ -117,13 +117,17 @@ void or_circuit_mul_tree(const or_keys* K, const uint32_t* A, const uint32_t* B,
  * tree-accumulated base product. */
 void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                           size_t count, int32_t width, int threads);
+/* (A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1). */
+void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                               size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
 /* The same circuits evaluated on plaintext bits (one byte per bit, operands
  * LSB first); returns the number of result bits written to out. */
 long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out);
 /* Number of bootstrapped gates the circuits above evaluate (no evaluation);
- * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba. */
+ * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba,
+ * 5 number-wise add. */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

@@ -19,12 +19,13 @@ def value(b):
 
 
 WANT = {"add": lambda a, b, w: (a + b) % (1 << w),
+        "add_numberwise": lambda a, b, w: (a + b) % (1 << w),
         "mul": lambda a, b, w: (a * b) % (1 << w),
         "mul_tree": lambda a, b, w: (a * b) % (1 << w),
         "karatsuba": lambda a, b, w: a * b}
 
 
-@pytest.mark.parametrize("kind", ["add", "mul", "mul_tree", "karatsuba"])
+@pytest.mark.parametrize("kind", ["add", "add_numberwise", "mul", "mul_tree", "karatsuba"])
 def test_exhaustive_narrow(kind):
     for w in range(2 if kind == "karatsuba" else 1, 6):
         for a in range(1 << w):
@@ -44,8 +45,11 @@ def test_random_wide_products(w):
         assert value(oracle.circuit_eval_plain("mul_tree", w, ab)) == (a * b) % (1 << w)
         assert value(oracle.circuit_eval_plain("mul", w, ab)) == (a * b) % (1 << w)
         assert value(oracle.circuit_eval_plain("add", w, ab)) == (a + b) % (1 << w)
+        assert value(oracle.circuit_eval_plain("add_numberwise", w, ab)) == (a + b) % (1 << w)
     top = (1 << w) - 1  # all ones: every carry chain at its longest
     assert value(oracle.circuit_eval_plain("karatsuba", w, bits(top, w) * 2)) == top * top
+    one = bits(1, w)  # 2^w - 1 + 1: a carry through every round of the number-wise adder
+    assert value(oracle.circuit_eval_plain("add_numberwise", w, bits(top, w) + one)) == 0
 
 
 def test_matvec_random():
@@ -67,3 +71,9 @@ def test_karatsuba_gate_counts():
         assert oracle.circuit_gate_count("karatsuba", w) >= w * w
     assert oracle.circuit_gate_count("karatsuba", 16) == 1457
     assert oracle.circuit_gate_count("karatsuba", 32) == 5271
+
+
+def test_numberwise_add_gate_count():
+    """Round k of the number-wise adder has w - k XORs and w - k - 1 ANDs."""
+    for w in range(1, 40):
+        assert oracle.circuit_gate_count("add_numberwise", w) == sum(2 * (w - k) - 1 for k in range(w)) == w * w

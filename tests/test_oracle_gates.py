@@ -151,6 +151,14 @@ def test_mul_tree_circuit_decrypts_to_low_product(okeys):
     np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a * b) % (1 << w))
 
 
+def test_numberwise_add_decrypts_to_sum(okeys):
+    w = 4
+    a = np.array([9, 15], np.uint64)
+    b = np.array([8, 1], np.uint64)
+    R = okeys.add_numberwise(okeys.encrypt_uint(a, w, nonce=76_000), okeys.encrypt_uint(b, w, nonce=86_000), w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a + b) % (1 << w))
+
+
 def test_karatsuba_circuit_decrypts_to_full_product(okeys):
     """Karatsuba's algorithm returns all 2w bits of the product (below 16 bits
     through its base product)."""
