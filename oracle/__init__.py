@@ -83,6 +83,7 @@ def lib():
             "or_circuit_mul_tree": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_karatsuba": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_add_numberwise": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_matmul": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_gate_count": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32]),
@@ -259,6 +260,14 @@ class Keys:
         lib().or_circuit_karatsuba(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
+    def matmul(self, A, B, n: int, width: int, threads: int = 0) -> np.ndarray:
+        """C = A B mod 2^width, n x n matrices, by Cannon's algorithm (Sec. V-B-3)."""
+        a = _c(A, np.uint32).reshape(n, n, width, self.width)
+        b = _c(B, np.uint32).reshape(n, n, width, self.width)
+        out = np.empty_like(a)
+        lib().or_circuit_matmul(self.ref(), _u32p(a), _u32p(b), _u32p(out), n, width, threads)
+        return out
+
     def matvec(self, M, x, rows: int, cols: int, width: int, threads: int = 0) -> np.ndarray:
         m = _c(M, np.uint32).reshape(rows, cols, width, self.width)
         v = _c(x, np.uint32).reshape(cols, width, self.width)
@@ -315,16 +324,18 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5}[kind]
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
+         "matmul": 6}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)
 
 
 def circuit_eval_plain(kind: str, width: int, operand_bits, rows: int = 0, cols: int = 0) -> np.ndarray:
     """A circuit's gates evaluated on plaintext bits (uint8 0/1, operands LSB
-    first, A then B or M then x); returns the result bits."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5}[kind]
+    first, A then B or M then x; matmul: rows = n); returns the result bits."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
+         "matmul": 6}[kind]
     bits = _c(operand_bits, np.uint8)
-    nout = rows * width if kind == "matvec" else (2 * width if kind == "karatsuba" else width)
+    nout = {"matvec": rows * width, "matmul": rows * rows * width, "karatsuba": 2 * width}.get(kind, width)
     out = np.empty(nout, np.uint8)
     got = lib().or_circuit_eval_plain(k, width, rows, cols, _u8p(bits), _u8p(out))
     assert got == nout

@@ -800,7 +800,8 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     free(o);
 }
 
-enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4, KIND_ADD_NUMBERWISE = 5 };
+enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4, KIND_ADD_NUMBERWISE = 5,
+       KIND_MATMUL = 6 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
@@ -879,6 +880,58 @@ static void build_matvec(or_prog* pr, int32_t rows, int32_t cols, int32_t w, lon
     free(prods);
 }
 
+/* C = A B mod 2^w for n x n matrices by Cannon's algorithm (Sec. V-B-3): after
+ * the initial skew (row i of A left by i, column j of B up by j) cycle t
+ * multiplies, in every cell at once, the aligned pair A[i][k] B[k][j] with
+ * k = (i + j + t) mod n, adds it to the cell's sum, and shifts A left and B
+ * up by one.  The shifts move no data in a circuit (they only rename wires);
+ * the products use the tree-accumulated multiplier (the paper's vector
+ * multiplication), the sums the ripple-carry adder, in cycle order.
+ * Wires: A then B, [n][n][w] each; cw: [n][n][w]. */
+static void build_matmul_cannon(or_prog* pr, int32_t n, int32_t w, long* cw) {
+    long* prod = (long*)malloc((size_t)w * sizeof(long));
+    long* sum = (long*)malloc((size_t)w * sizeof(long));
+    long ia[64], ib[64];
+    const long bbase = (long)n * n * w;
+    for (int32_t i = 0; i < n; i++)
+        for (int32_t j = 0; j < n; j++) {
+            long* c = cw + ((size_t)i * n + j) * w;
+            for (int32_t t = 0; t < n; t++) {
+                const int32_t k = (i + j + t) % n;
+                for (int32_t q = 0; q < w; q++) {
+                    ia[q] = ((long)i * n + k) * w + q;
+                    ib[q] = bbase + ((long)k * n + j) * w + q;
+                }
+                build_mul_tree(pr, ia, ib, w, t == 0 ? c : prod);
+                if (t > 0) {
+                    build_add(pr, c, prod, w, sum);
+                    memcpy(c, sum, (size_t)w * sizeof(long));
+                }
+            }
+        }
+    free(prod);
+    free(sum);
+}
+
+void or_circuit_matmul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* Cm,
+                       int32_t n, int32_t width, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    const size_t cells = (size_t)n * n;
+    or_prog pr = {0};
+    pr.nwires = (long)(2 * cells * (size_t)width);
+    long* cw = (long*)malloc(cells * (size_t)width * sizeof(long));
+    build_matmul_cannon(&pr, n, width, cw);
+    uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
+    memcpy(wires, A, cells * width * W * sizeof(uint32_t));
+    memcpy(wires + cells * width * W, B, cells * width * W * sizeof(uint32_t));
+    run_prog(K, &pr, wires, threads);
+    for (size_t q = 0; q < cells * (size_t)width; q++)
+        memcpy(Cm + q * W, wires + (size_t)cw[q] * W, W * sizeof(uint32_t));
+    free(wires);
+    free(cw);
+    free(pr.g);
+}
+
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads) {
     const size_t W = (size_t)K->P.n + 1;
@@ -914,8 +967,8 @@ static int plain_gate(int op, int a, int b) {
     }
 }
 
-/* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba,add_numberwise}
- * (kind 0..5)
+/* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba,add_numberwise,
+ * matmul} (kind 0..6; matmul: rows = n)
  * evaluated on plaintext bits, gate by gate in the order the program lists
  * them: in = operand bits (A then B, or M then x), LSB first, one byte per
  * bit; out = result bits.  Returns the number of result bits. */
@@ -929,6 +982,12 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
         pr.nwires = nin;
         res = (long*)malloc((size_t)nout * sizeof(long));
         build_matvec(&pr, rows, cols, width, res);
+    } else if (kind == KIND_MATMUL) { /* rows = n */
+        nin = 2L * rows * rows * width;
+        nout = (long)rows * rows * width;
+        pr.nwires = nin;
+        res = (long*)malloc((size_t)nout * sizeof(long));
+        build_matmul_cannon(&pr, rows, width, res);
     } else {
         nin = 2L * width;
         nout = kind == KIND_KARATSUBA ? 2L * width : width;
@@ -966,6 +1025,11 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
         long* yw = (long*)malloc((size_t)rows * width * sizeof(long));
         build_matvec(&pr, rows, cols, width, yw);
         free(yw);
+    } else if (kind == KIND_MATMUL) {
+        pr.nwires = 2L * rows * rows * width;
+        long* cw = (long*)malloc((size_t)rows * rows * width * sizeof(long));
+        build_matmul_cannon(&pr, rows, width, cw);
+        free(cw);
     } else {
         long* ia = (long*)malloc((size_t)width * sizeof(long));
         long* ib = (long*)malloc((size_t)width * sizeof(long));

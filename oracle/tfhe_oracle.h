@@ -122,12 +122,16 @@ void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32
                                size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
+/* C = A B mod 2^width (n x n matrices, [n][n][width][n+1] each) by Cannon's
+ * algorithm (Sec. V-B-3). */
+void or_circuit_matmul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* C,
+                       int32_t n, int32_t width, int threads);
 /* The same circuits evaluated on plaintext bits (one byte per bit, operands
  * LSB first); returns the number of result bits written to out. */
 long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out);
 /* Number of bootstrapped gates the circuits above evaluate (no evaluation);
  * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba,
- * 5 number-wise add. */
+ * 5 number-wise add, 6 Cannon matmul (rows = n). */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

@@ -77,3 +77,22 @@ def test_numberwise_add_gate_count():
     """Round k of the number-wise adder has w - k XORs and w - k - 1 ANDs."""
     for w in range(1, 40):
         assert oracle.circuit_gate_count("add_numberwise", w) == sum(2 * (w - k) - 1 for k in range(w)) == w * w
+
+
+def test_matmul_cannon_random():
+    """Cannon's algorithm (Sec. V-B-3) gives the matrix product mod 2^w."""
+    rng = np.random.default_rng(11)
+    for n, w in [(1, 5), (2, 4), (3, 6), (4, 16), (5, 3)]:
+        A = rng.integers(0, 1 << w, (n, n))
+        B = rng.integers(0, 1 << w, (n, n))
+        inp = sum((bits(v, w) for v in A.reshape(-1)), []) + sum((bits(v, w) for v in B.reshape(-1)), [])
+        out = oracle.circuit_eval_plain("matmul", w, inp, n)
+        got = np.array([value(out[q * w:(q + 1) * w]) for q in range(n * n)], dtype=object).reshape(n, n)
+        np.testing.assert_array_equal(got, (A.astype(object) @ B.astype(object)) % (1 << w))
+
+
+def test_matmul_cannon_gate_count():
+    """n^2 cells, each n tree products and n - 1 ripple additions."""
+    for n, w in [(1, 4), (2, 16), (4, 16), (3, 7)]:
+        want = n * n * (n * oracle.circuit_gate_count("mul_tree", w) + (n - 1) * oracle.circuit_gate_count("add", w))
+        assert oracle.circuit_gate_count("matmul", w, n) == want

@@ -170,6 +170,15 @@ def test_karatsuba_circuit_decrypts_to_full_product(okeys):
     np.testing.assert_array_equal(okeys.decrypt_uint(R, 2 * w), a * b)
 
 
+def test_matmul_cannon_decrypts_to_product(okeys):
+    w, n = 2, 2
+    A = np.array([[3, 2], [1, 3]], np.uint64)
+    B = np.array([[2, 3], [3, 1]], np.uint64)
+    C = okeys.matmul(okeys.encrypt_uint(A.reshape(-1), w, nonce=92_000),
+                     okeys.encrypt_uint(B.reshape(-1), w, nonce=93_000), n, w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(C.reshape(n * n, w, -1), w).reshape(n, n), (A @ B) % (1 << w))
+
+
 def test_matvec_circuit_decrypts_to_product(okeys):
     w, rows, cols = 2, 2, 2
     M = np.array([[3, 2], [1, 3]], np.uint64)
