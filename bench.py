@@ -383,6 +383,43 @@ def main():
                     "samples": len(kl), "gates": kg, "levels": klv, "product_bits": 64}
         log(f"mul32 Karatsuba (64-bit product) latency: {mul_kara}")
 
+    # latency of other circuits of the paper, one instance each: the 16-bit
+    # adders (ripple carry, eqs. (1)-(2); number-wise, GPU_n) and the 4 x 4
+    # 16-bit matrix product by Cannon's algorithm
+    circuits = None
+    if args.mul_samples > 0:
+        ca = workloads.uniform_uints(13, 1, 16)
+        cb = workloads.uniform_uints(14, 1, 16)
+        cA = F.to_device(sk.encrypt_uint(ca, 16, nonce=(1 << 52) + 128))
+        cB = F.to_device(sk.encrypt_uint(cb, 16, nonce=(1 << 52) + 160))
+        cR = torch.empty_like(cA)
+        rng = np.random.default_rng(15)
+        MA = rng.integers(0, 1 << 16, (4, 4)).astype(np.uint64)
+        MB = rng.integers(0, 1 << 16, (4, 4)).astype(np.uint64)
+        dMA = F.to_device(sk.encrypt_uint(MA.reshape(-1), 16, nonce=(1 << 52) + 1024))
+        dMB = F.to_device(sk.encrypt_uint(MB.reshape(-1), 16, nonce=(1 << 52) + 2048))
+        dMC = torch.empty_like(dMA)
+        legs = {"add16": (lambda: F.fhe_add(ctx, cA, cB, cR, 1, 16, stream), ("add", 16, 0)),
+                "add16_numberwise": (lambda: F.fhe_add_numberwise(ctx, cA, cB, cR, 1, 16, stream),
+                                     ("add_numberwise", 16, 0)),
+                "matmul4x4_16": (lambda: F.fhe_matmul(ctx, dMA, dMB, dMC, 4, 16, stream), ("matmul", 16, 4))}
+        circuits = {}
+        for name, (fn, shape) in legs.items():
+            fn()
+            torch.cuda.synchronize()
+            tl = []
+            for _ in range(args.mul_samples):
+                s0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                tl.append(time.perf_counter() - s0)
+            g, lv, _ = F.fhe_circuit_shape(shape[0], shape[1], shape[2])
+            circuits[name] = {"p50_ms": round(1e3 * float(np.median(tl)), 1), "gates": g, "levels": lv}
+        assert sk.decrypt_uint(F.to_host(cR), 16)[0] == (int(ca[0]) + int(cb[0])) % (1 << 16)
+        got = sk.decrypt_uint(F.to_host(dMC).reshape(16, 16, -1), 16).reshape(4, 4).astype(object)
+        assert (got == (MA.astype(object) @ MB.astype(object)) % (1 << 16)).all()
+        log(f"circuit latency: {circuits}")
+
     serving = None
     if args.serve_jobs > 0:
         log(f"serving: {args.serve_jobs} jobs at {args.serve_load:.2f} x {value:.0f} gates/s")
@@ -405,7 +442,7 @@ def main():
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": workload,
         "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
-        "mul32_karatsuba_latency": mul_kara, "serving": serving,
+        "mul32_karatsuba_latency": mul_kara, "circuit_latency": circuits, "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": per_shape},

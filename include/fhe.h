@@ -183,6 +183,15 @@ int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
 int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
             uint32_t width, void* stream);
 
+/* R = (A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1): w rounds
+ * of carry = R & B, R = R ^ B, B = carry << 1 over all bits at once (the
+ * round's AND and XOR side by side).  width^2 gates in width levels (16 bits:
+ * 256 gates, 16 levels, against 74 gates in 30 levels for fhe_add): fewer
+ * levels, more gates.  Output words differ from fhe_add's; buffers and errors
+ * as fhe_add. */
+int fhe_add_numberwise(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                       uint32_t width, void* stream);
+
 /* R = (A * B) mod 2^width, shift-and-add multiplier (Sec. III-B-1) keeping the
  * low width bits. */
 int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
@@ -214,6 +223,17 @@ int fhe_mul_karatsuba(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32
  * y: [rows][width][n+1]. */
 int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, uint32_t rows,
                uint32_t cols, uint32_t width, void* stream);
+
+/* C = A B mod 2^width for n x n matrices by Cannon's algorithm (Sec. V-B-3):
+ * in cycle t cell (i, j) multiplies A[i][k] B[k][j], k = (i + j + t) mod n
+ * (the skew and shifts rename wires, no data moves), with the tree
+ * multiplier of fhe_mul_tree, and adds the product to the cell's sum in cycle
+ * order with the ripple-carry adder.  All cycles' products are independent,
+ * so the level schedule runs them side by side (HBM holds every sample).
+ * A, B, C: device uint32[n][n][width][n+1].  EINVAL: n outside 1..64, width
+ * outside 1..64, null buffers. */
+int fhe_matmul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* C, uint32_t n,
+               uint32_t width, void* stream);
 
 /* Circuit calls replay their level schedule as a captured HIP graph (one
  * per circuit shape and set of buffers, captured on first use; kernel
@@ -264,7 +284,8 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
 
 /* Number of gates and of levels of a circuit as the library schedules it
  * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation,
- * 4 = Karatsuba; rows/cols only for matvec). */
+ * 4 = Karatsuba, 5 = number-wise add, 6 = Cannon matmul with rows = n;
+ * rows/cols only for matvec and matmul). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 

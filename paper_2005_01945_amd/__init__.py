@@ -67,6 +67,8 @@ _SIGS = {
     "fhe_add": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul_tree": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_add_numberwise": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
     "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -277,6 +279,11 @@ def fhe_add(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_add(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_add")
 
 
+def fhe_add_numberwise(ctx, A, B, R, count, width, stream=None):
+    _check(lib().fhe_add_numberwise(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)),
+           "fhe_add_numberwise")
+
+
 def fhe_mul(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_mul(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_mul")
 
@@ -296,9 +303,15 @@ def fhe_matvec(ctx, M, x, y, rows, cols, width, stream=None):
            "fhe_matvec")
 
 
+def fhe_matmul(ctx, A, B, Cm, n, width, stream=None):
+    """C = A B mod 2^width (n x n) by Cannon's algorithm."""
+    _check(lib().fhe_matmul(ctx.h, _dev(A), _dev(B), _dev(Cm), n, width, _stream(stream)), "fhe_matmul")
+
+
 def fhe_circuit_shape(kind, width, rows=0, cols=0):
-    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree', 'karatsuba'}."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4}[kind]
+    """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree',
+    'karatsuba', 'add_numberwise', 'matmul'} (matmul: rows = n)."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6}[kind]
     g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")

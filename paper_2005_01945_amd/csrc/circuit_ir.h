@@ -7,7 +7,7 @@
 
 namespace fhe {
 
-enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3, kKaratsuba = 4 };
+enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3, kKaratsuba = 4, kAddNumberwise = 5, kMatmul = 6 };
 
 struct Gate {
     uint8_t op;
@@ -24,9 +24,9 @@ struct Circuit {
     uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
 };
 
-// kind: kAdd / kMul / kMulTree / kKaratsuba (operands of width w; Karatsuba
-// has 2w result bits) or kMatvec (rows x cols matrix of w-bit entries times a
-// cols-vector).
+// kind: kAdd / kAddNumberwise / kMul / kMulTree / kKaratsuba (operands of
+// width w; Karatsuba has 2w result bits), kMatvec (rows x cols matrix of w-bit
+// entries times a cols-vector) or kMatmul (two rows x rows matrices).
 Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols);
 
 // ASAP level of every gate (inputs are level 0); *depth = deepest level.

@@ -6,6 +6,9 @@
 //      bit 0:     r = a^b,            c = a&b
 //      bit i:     t = a^b, g = a&b,  r = t^c, h = t&c, c = g|h
 //      bit w-1:   t = a^b,            r = t^c      (carry out dropped)
+//  - number-wise add (GPU_n, Sec. V-B-1), sum mod 2^w: R = A, then w rounds
+//    of carry = R & B, R = R ^ B, B = carry << 1, each round on the bits of B
+//    not yet known zero (round k: bits k..w-1): w^2 gates in w levels.
 //  - mul, low w bits: naive shift-and-add (Sec. III-B-1):
 //      acc = A & b_0;  acc[i..w-1] += (A & b_i)[0..w-1-i] for i = 1..w-1
 //  - mul with tree accumulation (Sec. V-B-2, Fig. 4), low w bits: partial
@@ -21,6 +24,10 @@
 //    Z1 = X1 Y1, Z2 = (X0 + X1)(Y0 + Y1), M = Z2 - (Z0 + Z1) mod 2^(w+1)
 //    (subtraction as x + ~y + 1: XNOR / ANDYN gates, the +1 folded into bit
 //    0 as XOR / ORYN), Z = (Z0 | Z1 << 2h) + M << h.
+//  - matmul, n x n, by Cannon's algorithm (Sec. V-B-3): cell (i, j) in cycle
+//    t multiplies A[i][k] B[k][j], k = (i + j + t) mod n (the skew and the
+//    per-cycle shifts only rename wires), with the tree multiplier, and adds
+//    the product to its sum in cycle order with the ripple-carry adder.
 //  - matvec: every product by mul; each row's products accumulated by the
 //    tree of Sec. V-B-2 / Fig. 4: the list is split into first and second
 //    halves that are added element-wise, an odd last element waits a round.
@@ -76,6 +83,16 @@ class Builder {
             r[i] = gate(FHE_XOR, t, carry);
             const uint32_t h = gate(FHE_AND, t, carry);
             carry = gate(FHE_OR, g, h);
+        }
+        return r;
+    }
+    std::vector<uint32_t> add_numberwise(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t w = a.size();
+        std::vector<uint32_t> r(a), sh(b), carry(w);
+        for (size_t k = 0; k < w; ++k) {
+            for (size_t i = k; i + 1 < w; ++i) carry[i] = gate(FHE_AND, r[i], sh[i]);
+            for (size_t i = k; i < w; ++i) r[i] = gate(FHE_XOR, r[i], sh[i]);
+            for (size_t i = w - 1; i > k; --i) sh[i] = carry[i - 1];  // bit k of B is now zero
         }
         return r;
     }
@@ -257,6 +274,22 @@ static std::vector<uint32_t> iota_wires(uint32_t first, uint32_t count) {
 }
 
 Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
+    if (kind == kMatmul) {  // rows = n
+        const uint32_t n = rows;
+        Builder B(n * n * w, n * n * w);
+        for (uint32_t i = 0; i < n; ++i)
+            for (uint32_t j = 0; j < n; ++j) {
+                std::vector<uint32_t> c;
+                for (uint32_t t = 0; t < n; ++t) {
+                    const uint32_t k = (i + j + t) % n;
+                    const std::vector<uint32_t> p =
+                        B.mul_tree(iota_wires((i * n + k) * w, w), iota_wires(n * n * w + (k * n + j) * w, w));
+                    c = t == 0 ? p : B.add(c, p);
+                }
+                B.c.outputs.insert(B.c.outputs.end(), c.begin(), c.end());
+            }
+        return B.c;
+    }
     if (kind == kMatvec) {
         Builder B(rows * cols * w, cols * w);
         for (uint32_t r = 0; r < rows; ++r) {
@@ -271,6 +304,7 @@ Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
     Builder B(w, w);
     const std::vector<uint32_t> a = iota_wires(0, w), b = iota_wires(w, w);
     B.c.outputs = kind == kAdd        ? B.add(a, b)
+                  : kind == kAddNumberwise ? B.add_numberwise(a, b)
                   : kind == kMulTree  ? B.mul_tree(a, b)
                   : kind == kKaratsuba ? B.karatsuba(a, b)
                                        : B.mul(a, b);
@@ -500,6 +534,11 @@ extern "C" int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint3
     return run_circuit(ctx, kAdd, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add");
 }
 
+extern "C" int fhe_add_numberwise(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                                  uint32_t width, void* stream) {
+    return run_circuit(ctx, kAddNumberwise, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add_numberwise");
+}
+
 extern "C" int fhe_mul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
                        uint32_t width, void* stream) {
     return run_circuit(ctx, kMul, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_mul");
@@ -522,9 +561,16 @@ extern "C" int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, ui
     return run_circuit(ctx, kMatvec, M, x, y, 1, width, rows, cols, (hipStream_t)stream, "fhe_matvec");
 }
 
+extern "C" int fhe_matmul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* C, uint32_t n,
+                          uint32_t width, void* stream) {
+    if (n == 0 || n > 64) return set_error(FHE_EINVAL, "fhe_matmul: dimension %u not in 1..64", n);
+    return run_circuit(ctx, kMatmul, A, B, C, 1, width, n, 0, (hipStream_t)stream, "fhe_matmul");
+}
+
 extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,
                                  uint32_t* levels, uint64_t* widest_level) {
-    if (kind < 0 || kind > 4 || width < 1 || (kind == kKaratsuba && width < 2) || width > 64 || (kind == kMatvec && (rows == 0 || cols == 0)))
+    if (kind < 0 || kind > 6 || width < 1 || (kind == kKaratsuba && width < 2) || width > 64 ||
+        (kind == kMatvec && (rows == 0 || cols == 0)) || (kind == kMatmul && (rows == 0 || rows > 64)))
         return set_error(FHE_EINVAL, "fhe_circuit_shape: bad arguments");
     const Circuit c = build_circuit(kind, width, rows, cols);
     uint32_t depth = 0;

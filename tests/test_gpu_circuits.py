@@ -180,6 +180,45 @@ def test_karatsuba32_full_products_decrypt(env):
     np.testing.assert_array_equal(got, a.astype(object) * b.astype(object))
 
 
+@pytest.mark.parametrize("n,width", [(2, 3), (3, 2)])
+def test_matmul_cannon_bit_exact(env, n, width):
+    """Cannon's algorithm (Sec. V-B-3) against the oracle."""
+    import torch
+    sk, ctx, K = env
+    rng = np.random.default_rng(100 + n)
+    A = rng.integers(0, 1 << width, (n, n)).astype(np.uint64)
+    B = rng.integers(0, 1 << width, (n, n)).astype(np.uint64)
+    cA = sk.encrypt_uint(A.reshape(-1), width, nonce=1_900_000)
+    cB = sk.encrypt_uint(B.reshape(-1), width, nonce=2_000_000)
+    dA, dB = F.to_device(cA), F.to_device(cB)
+    dC = torch.empty_like(dA)
+    log(f"matmul n={n} width={width}")
+    F.fhe_matmul(ctx, dA, dB, dC, n, width)
+    torch.cuda.synchronize()
+    got = F.to_host(dC)
+    np.testing.assert_array_equal(sk.decrypt_uint(got.reshape(n * n, width, -1), width).reshape(n, n),
+                                  (A @ B) % (1 << width))
+    log(f"oracle: matmul n={n} width={width}")
+    np.testing.assert_array_equal(got.reshape(n, n, width, -1), K.matmul(cA, cB, n, width))
+
+
+def test_matmul16_4x4_decrypts(env):
+    """The 4 x 4 16-bit product (45,024 gates)."""
+    import torch
+    sk, ctx, K = env
+    rng = np.random.default_rng(104)
+    A = rng.integers(0, 1 << 16, (4, 4)).astype(np.uint64)
+    B = rng.integers(0, 1 << 16, (4, 4)).astype(np.uint64)
+    dA = F.to_device(sk.encrypt_uint(A.reshape(-1), 16, nonce=2_100_000))
+    dB = F.to_device(sk.encrypt_uint(B.reshape(-1), 16, nonce=2_200_000))
+    dC = torch.empty_like(dA)
+    log("matmul 4x4 16-bit")
+    F.fhe_matmul(ctx, dA, dB, dC, 4, 16)
+    torch.cuda.synchronize()
+    got = sk.decrypt_uint(F.to_host(dC).reshape(16, 16, -1), 16).reshape(4, 4).astype(object)
+    np.testing.assert_array_equal(got, (A.astype(object) @ B.astype(object)) % (1 << 16))
+
+
 def test_mul32_full_size_decrypts(env):
     """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
     product decrypts correctly."""

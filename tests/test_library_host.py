@@ -124,6 +124,8 @@ def test_circuit_shapes_match_oracle_gate_counts():
         assert F.fhe_circuit_shape("karatsuba", w)[0] == oracle.circuit_gate_count("karatsuba", w)
         assert F.fhe_circuit_shape("add_numberwise", w)[0] == oracle.circuit_gate_count("add_numberwise", w)
     assert F.fhe_circuit_shape("add_numberwise", 16) == (256, 16, 31)
+    for n, w in [(1, 3), (2, 16), (3, 5), (4, 16)]:
+        assert F.fhe_circuit_shape("matmul", w, n)[0] == oracle.circuit_gate_count("matmul", w, n)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64)[0] == oracle.circuit_gate_count("matvec", 16, 64, 64)
     assert F.fhe_circuit_shape("matvec", 3, 5, 7)[0] == oracle.circuit_gate_count("matvec", 3, 5, 7)
     # gates, ASAP depth, widest level of the paper-sized circuits
