@@ -19,6 +19,7 @@ _lib = None
 
 AND, NAND, OR, NOR, XOR, XNOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
 GATE_NAMES = ["AND", "NAND", "OR", "NOR", "XOR", "XNOR", "ANDNY", "ANDYN", "ORNY", "ORYN"]
+MAJ, XOR3 = 10, 11  # three-input gates: majority and parity
 MU = 1 << 29
 
 
@@ -84,6 +85,8 @@ def lib():
             "or_circuit_karatsuba": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_add_numberwise": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_matmul": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int]),
+            "or_circuit_add_fa": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_bootstrap_gates3": (None, [KP, u8p, u32p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_gate_count": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32]),
@@ -244,6 +247,24 @@ class Keys:
         lib().or_circuit_mul_tree(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
+    def add_fa(self, A, B, width: int, threads: int = 0) -> np.ndarray:
+        """(A + B) mod 2^width, ripple carry of full-adder gates (MAJ, XOR3)."""
+        a = _c(A, np.uint32).reshape(-1, width, self.width)
+        b = _c(B, np.uint32).reshape(-1, width, self.width)
+        out = np.empty_like(a)
+        lib().or_circuit_add_fa(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
+    def bootstrap3(self, ops, in0, in1, in2, threads: int = 0) -> np.ndarray:
+        """Bootstrapped gates of up to three inputs (MAJ = 10, XOR3 = 11)."""
+        o = _c(ops, np.uint8)
+        a = _c(in0, np.uint32).reshape(-1, self.width)
+        b = _c(in1, np.uint32).reshape(-1, self.width)
+        c = _c(in2, np.uint32).reshape(-1, self.width)
+        out = np.empty((o.size, self.width), np.uint32)
+        lib().or_bootstrap_gates3(self.ref(), _u8p(o), _u32p(a), _u32p(b), _u32p(c), _u32p(out), o.size, threads)
+        return out
+
     def add_numberwise(self, A, B, width: int, threads: int = 0) -> np.ndarray:
         """(A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1)."""
         a = _c(A, np.uint32).reshape(-1, width, self.width)
@@ -325,7 +346,7 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
     k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
-         "matmul": 6}[kind]
+         "matmul": 6, "add_fa": 7}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)
 
 
@@ -333,7 +354,7 @@ def circuit_eval_plain(kind: str, width: int, operand_bits, rows: int = 0, cols:
     """A circuit's gates evaluated on plaintext bits (uint8 0/1, operands LSB
     first, A then B or M then x; matmul: rows = n); returns the result bits."""
     k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
-         "matmul": 6}[kind]
+         "matmul": 6, "add_fa": 7}[kind]
     bits = _c(operand_bits, np.uint8)
     nout = {"matvec": rows * width, "matmul": rows * rows * width, "karatsuba": 2 * width}.get(kind, width)
     out = np.empty(nout, np.uint8)

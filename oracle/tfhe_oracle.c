@@ -375,6 +375,35 @@ void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out) {
     }
 }
 
+/* Three-input gates (encoding +-mu, mu = 1/8): c1 + c2 + c3 has phase
+ * -3/8, -1/8, 1/8 or 3/8 for 0, 1, 2 or 3 true inputs, positive iff most are
+ * true (MAJ); -2 (c1 + c2 + c3) has phase 3/4 = -1/4, 1/4, -1/4 or -3/4 =
+ * 1/4, positive iff an odd number is true (XOR3).  No constant is added. */
+void or_gate_combine3(const or_params* P, int op, const uint32_t* c1, const uint32_t* c2,
+                      const uint32_t* c3, uint32_t* out) {
+    if (op != OR_MAJ && op != OR_XOR3) {
+        or_gate_combine(P, op, c1, c2, out);
+        return;
+    }
+    const uint32_t s = op == OR_MAJ ? 1u : 0u - 2u;
+    for (int32_t i = 0; i <= P->n; i++) out[i] = s * (c1[i] + c2[i] + c3[i]);
+}
+
+void or_bootstrap_gate3(const or_keys* K, int op, const uint32_t* c1, const uint32_t* c2,
+                        const uint32_t* c3, uint32_t* out) {
+    const or_params* P = &K->P;
+    uint32_t* comb = (uint32_t*)malloc((size_t)(P->n + 1) * sizeof(uint32_t));
+    uint32_t* acc = (uint32_t*)malloc(2u * (size_t)P->N * sizeof(uint32_t));
+    uint32_t* big = (uint32_t*)malloc((size_t)(P->N + 1) * sizeof(uint32_t));
+    or_gate_combine3(P, op, c1, c2, c3, comb);
+    or_blind_rotate(K, comb, acc);
+    or_sample_extract(P, acc, big);
+    or_key_switch(K, big, out);
+    free(comb);
+    free(acc);
+    free(big);
+}
+
 void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,
                        const uint32_t* c2, uint32_t* out) {
     const or_params* P = &K->P;
@@ -398,6 +427,7 @@ typedef struct {
     const uint8_t* ops;
     const uint32_t* const* in0;
     const uint32_t* const* in1;
+    const uint32_t* const* in2; /* NULL: two-input gates only */
     uint32_t* const* out;
     size_t count;
     size_t next;
@@ -411,7 +441,10 @@ static void* gate_worker(void* arg) {
         size_t g = J->next++;
         pthread_mutex_unlock(&J->lock);
         if (g >= J->count) break;
-        or_bootstrap_gate(J->K, J->ops[g], J->in0[g], J->in1[g], J->out[g]);
+        if (J->in2)
+            or_bootstrap_gate3(J->K, J->ops[g], J->in0[g], J->in1[g], J->in2[g], J->out[g]);
+        else
+            or_bootstrap_gate(J->K, J->ops[g], J->in0[g], J->in1[g], J->out[g]);
     }
     return NULL;
 }
@@ -425,14 +458,15 @@ static int resolve_threads(int threads) {
 
 /* Runs gate g on (in0[g], in1[g]) -> out[g] for g < count, pointer form. */
 static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* const* in0,
-                      const uint32_t* const* in1, uint32_t* const* out, size_t count,
-                      int threads) {
+                      const uint32_t* const* in1, const uint32_t* const* in2, uint32_t* const* out,
+                      size_t count, int threads) {
     if (count == 0) return;
     gate_job J;
     J.K = K;
     J.ops = ops;
     J.in0 = in0;
     J.in1 = in1;
+    J.in2 = in2;
     J.out = out;
     J.count = count;
     J.next = 0;
@@ -457,21 +491,41 @@ void or_bootstrap_gates(const or_keys* K, const uint8_t* ops, const uint32_t* in
         b[g] = in1 + g * W;
         o[g] = out + g * W;
     }
-    run_gates(K, ops, a, b, o, count, threads);
+    run_gates(K, ops, a, b, NULL, o, count, threads);
     free(a);
     free(b);
+    free(o);
+}
+
+void or_bootstrap_gates3(const or_keys* K, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                         const uint32_t* in2, uint32_t* out, size_t count, int threads) {
+    const size_t W = (size_t)K->P.n + 1;
+    const uint32_t** a = (const uint32_t**)malloc((count + 1) * sizeof(*a));
+    const uint32_t** b = (const uint32_t**)malloc((count + 1) * sizeof(*b));
+    const uint32_t** c = (const uint32_t**)malloc((count + 1) * sizeof(*c));
+    uint32_t** o = (uint32_t**)malloc((count + 1) * sizeof(*o));
+    for (size_t g = 0; g < count; g++) {
+        a[g] = in0 + g * W;
+        b[g] = in1 + g * W;
+        c[g] = in2 + g * W;
+        o[g] = out + g * W;
+    }
+    run_gates(K, ops, a, b, c, o, count, threads);
+    free(a);
+    free(b);
+    free(c);
     free(o);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Circuits as gate lists over wires (each wire holds one LWE sample).        */
 /* ------------------------------------------------------------------------ */
-typedef struct { int op, in0, in1, out; } or_gate_t;
+typedef struct { int op, in0, in1, in2, out; } or_gate_t; /* in2 < 0: two inputs */
 typedef struct { or_gate_t* g; long ng, cap; long nwires; } or_prog;
 
 static long new_wire(or_prog* pr) { return pr->nwires++; }
 
-static long emit(or_prog* pr, int op, long a, long b) {
+static long emit3(or_prog* pr, int op, long a, long b, long c) {
     if (pr->ng == pr->cap) {
         pr->cap = pr->cap ? 2 * pr->cap : 256;
         pr->g = (or_gate_t*)realloc(pr->g, (size_t)pr->cap * sizeof(or_gate_t));
@@ -481,9 +535,12 @@ static long emit(or_prog* pr, int op, long a, long b) {
     G->op = op;
     G->in0 = (int)a;
     G->in1 = (int)b;
+    G->in2 = (int)c;
     G->out = (int)o;
     return o;
 }
+
+static long emit(or_prog* pr, int op, long a, long b) { return emit3(pr, op, a, b, -1); }
 
 /* Ripple-carry adder of eqs. (1)-(2), sum modulo 2^w (carry out dropped):
  *   bit 0:     r = a ^ b,            c = a & b
@@ -567,6 +624,21 @@ static void build_mul_tree(or_prog* pr, const long* a, const long* b, int w, lon
     free(bits);
     free(low);
     free(sum);
+}
+
+/* Ripple-carry adder of full-adder gates, sum mod 2^w: bit 0 r = a ^ b,
+ * c = a & b; bit i: r = XOR3(a, b, c), c = MAJ(a, b, c) (eqs. (1)-(2) with
+ * the sum and carry of each bit as one three-input gate each); the top bit
+ * r = XOR3(a, b, c) only.  2w - 1 gates (w > 1) in w levels. */
+static void build_add_fa(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    if (w <= 0) return;
+    r[0] = emit(pr, OR_XOR, a[0], b[0]);
+    if (w == 1) return;
+    long c = emit(pr, OR_AND, a[0], b[0]);
+    for (int i = 1; i < w; i++) {
+        r[i] = emit3(pr, OR_XOR3, a[i], b[i], c);
+        if (i + 1 < w) c = emit3(pr, OR_MAJ, a[i], b[i], c);
+    }
 }
 
 /* Number-wise addition (GPU_n, Sec. V-B-1), sum mod 2^w: R = A; then w
@@ -772,36 +844,42 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     long maxlev = 0;
     for (long k = 0; k < pr->ng; k++) {
         const or_gate_t* G = &pr->g[k];
-        long l0 = level[G->in0], l1 = level[G->in1];
-        level[G->out] = 1 + (l0 > l1 ? l0 : l1);
+        long l = level[G->in0] > level[G->in1] ? level[G->in0] : level[G->in1];
+        if (G->in2 >= 0 && level[G->in2] > l) l = level[G->in2];
+        level[G->out] = 1 + l;
         if (level[G->out] > maxlev) maxlev = level[G->out];
     }
     uint8_t* ops = (uint8_t*)malloc((size_t)pr->ng + 1);
     const uint32_t** a = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*a));
     const uint32_t** b = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*b));
+    const uint32_t** c = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*c));
     uint32_t** o = (uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*o));
     for (long L = 1; L <= maxlev; L++) {
         size_t cnt = 0;
+        int three = 0;
         for (long k = 0; k < pr->ng; k++) {
             const or_gate_t* G = &pr->g[k];
             if (level[G->out] != L) continue;
             ops[cnt] = (uint8_t)G->op;
             a[cnt] = wires + (size_t)G->in0 * W;
             b[cnt] = wires + (size_t)G->in1 * W;
+            c[cnt] = G->in2 >= 0 ? wires + (size_t)G->in2 * W : a[cnt]; /* (unread by two-input gates) */
+            three |= G->in2 >= 0;
             o[cnt] = wires + (size_t)G->out * W;
             cnt++;
         }
-        run_gates(K, ops, a, b, o, cnt, threads);
+        run_gates(K, ops, a, b, three ? c : NULL, o, cnt, threads);
     }
     free(level);
     free(ops);
     free(a);
     free(b);
+    free(c);
     free(o);
 }
 
 enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4, KIND_ADD_NUMBERWISE = 5,
-       KIND_MATMUL = 6 };
+       KIND_MATMUL = 6, KIND_ADD_FA = 7 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
@@ -821,6 +899,7 @@ static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const 
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, outw + c * ow);
+        else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, outw + c * ow);
         else build_mul(&pr, ia, ib, width, outw + c * ow);
     }
     uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
@@ -859,6 +938,11 @@ void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B
 void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                                size_t count, int32_t width, int threads) {
     circuit_binary(K, KIND_ADD_NUMBERWISE, A, B, R, count, width, threads);
+}
+
+void or_circuit_add_fa(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                       size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_ADD_FA, A, B, R, count, width, threads);
 }
 
 /* y_r = sum_c M[r][c] * x_c mod 2^w: every product by the shift-and-add multiplier,
@@ -968,7 +1052,7 @@ static int plain_gate(int op, int a, int b) {
 }
 
 /* The circuit of or_circuit_{add,mul,matvec,mul_tree,karatsuba,add_numberwise,
- * matmul} (kind 0..6; matmul: rows = n)
+ * matmul,add_fa} (kind 0..7; matmul: rows = n)
  * evaluated on plaintext bits, gate by gate in the order the program lists
  * them: in = operand bits (A then B, or M then x), LSB first, one byte per
  * bit; out = result bits.  Returns the number of result bits. */
@@ -1000,6 +1084,7 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, res);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, res);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, res);
+        else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, res);
         else build_mul(&pr, ia, ib, width, res);
         free(ia);
         free(ib);
@@ -1008,7 +1093,12 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
     memcpy(v, in, (size_t)nin);
     for (long k = 0; k < pr.ng; k++) {
         const or_gate_t* G = &pr.g[k];
-        v[G->out] = (uint8_t)plain_gate(G->op, v[G->in0], v[G->in1]);
+        if (G->in2 >= 0) {
+            const int n1 = v[G->in0] + v[G->in1] + v[G->in2];
+            v[G->out] = (uint8_t)(G->op == OR_MAJ ? n1 >= 2 : n1 & 1);
+        } else {
+            v[G->out] = (uint8_t)plain_gate(G->op, v[G->in0], v[G->in1]);
+        }
     }
     for (long q = 0; q < nout; q++) out[q] = v[res[q]];
     free(v);
@@ -1040,6 +1130,7 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
         else if (kind == KIND_MUL_TREE) build_mul_tree(&pr, ia, ib, width, r);
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, r);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, r);
+        else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, r);
         else build_mul(&pr, ia, ib, width, r);
         free(ia);
         free(ib);

@@ -61,6 +61,10 @@ typedef struct {
 /* Gate codes (uint8 on the wire), same numbering as the public gate enum. */
 enum { OR_AND = 0, OR_NAND, OR_OR, OR_NOR, OR_XOR, OR_XNOR,
        OR_ANDNY, OR_ANDYN, OR_ORNY, OR_ORYN, OR_NUM_GATES };
+/* Three-input gates: majority (the sign of c1 + c2 + c3, a full adder's
+ * carry) and parity (the sign of -2 (c1 + c2 + c3), its sum bit).  Both read
+ * the same constant test vector as the two-input gates. */
+enum { OR_MAJ = 10, OR_XOR3 = 11 };
 
 /* ---- counter-based generator (SplitMix64 output function) ---- */
 uint64_t or_mix64(uint64_t z);
@@ -98,6 +102,16 @@ void or_sample_extract(const or_params* P, const uint32_t* acc, uint32_t* lwe_bi
 void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out);
 
 /* One bootstrapped gate; threads = 0 means all online cores. */
+/* Linear combination of a three-input gate (OR_MAJ, OR_XOR3; a two-input
+ * code ignores c3). */
+void or_gate_combine3(const or_params* P, int op, const uint32_t* c1, const uint32_t* c2,
+                      const uint32_t* c3, uint32_t* out);
+/* Bootstrapped gate of up to three inputs. */
+void or_bootstrap_gate3(const or_keys* K, int op, const uint32_t* c1, const uint32_t* c2,
+                        const uint32_t* c3, uint32_t* out);
+/* out[g] = ops[g](in0[g], in1[g], in2[g]), independent gates on `threads`. */
+void or_bootstrap_gates3(const or_keys* K, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                         const uint32_t* in2, uint32_t* out, size_t count, int threads);
 void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,
                        const uint32_t* c2, uint32_t* out);
 void or_bootstrap_gates(const or_keys* K, const uint8_t* ops, const uint32_t* in0,
@@ -122,6 +136,9 @@ void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32
                                size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
+/* (A + B) mod 2^width by a ripple carry of full-adder gates (XOR3, MAJ). */
+void or_circuit_add_fa(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                       size_t count, int32_t width, int threads);
 /* C = A B mod 2^width (n x n matrices, [n][n][width][n+1] each) by Cannon's
  * algorithm (Sec. V-B-3). */
 void or_circuit_matmul(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* C,
@@ -131,7 +148,7 @@ void or_circuit_matmul(const or_keys* K, const uint32_t* A, const uint32_t* B, u
 long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out);
 /* Number of bootstrapped gates the circuits above evaluate (no evaluation);
  * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba,
- * 5 number-wise add, 6 Cannon matmul (rows = n). */
+ * 5 number-wise add, 6 Cannon matmul (rows = n), 7 full-adder add. */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

@@ -20,12 +20,13 @@ def value(b):
 
 WANT = {"add": lambda a, b, w: (a + b) % (1 << w),
         "add_numberwise": lambda a, b, w: (a + b) % (1 << w),
+        "add_fa": lambda a, b, w: (a + b) % (1 << w),
         "mul": lambda a, b, w: (a * b) % (1 << w),
         "mul_tree": lambda a, b, w: (a * b) % (1 << w),
         "karatsuba": lambda a, b, w: a * b}
 
 
-@pytest.mark.parametrize("kind", ["add", "add_numberwise", "mul", "mul_tree", "karatsuba"])
+@pytest.mark.parametrize("kind", ["add", "add_numberwise", "add_fa", "mul", "mul_tree", "karatsuba"])
 def test_exhaustive_narrow(kind):
     for w in range(2 if kind == "karatsuba" else 1, 6):
         for a in range(1 << w):
@@ -46,6 +47,7 @@ def test_random_wide_products(w):
         assert value(oracle.circuit_eval_plain("mul", w, ab)) == (a * b) % (1 << w)
         assert value(oracle.circuit_eval_plain("add", w, ab)) == (a + b) % (1 << w)
         assert value(oracle.circuit_eval_plain("add_numberwise", w, ab)) == (a + b) % (1 << w)
+        assert value(oracle.circuit_eval_plain("add_fa", w, ab)) == (a + b) % (1 << w)
     top = (1 << w) - 1  # all ones: every carry chain at its longest
     assert value(oracle.circuit_eval_plain("karatsuba", w, bits(top, w) * 2)) == top * top
     one = bits(1, w)  # 2^w - 1 + 1: a carry through every round of the number-wise adder
@@ -96,3 +98,10 @@ def test_matmul_cannon_gate_count():
     for n, w in [(1, 4), (2, 16), (4, 16), (3, 7)]:
         want = n * n * (n * oracle.circuit_gate_count("mul_tree", w) + (n - 1) * oracle.circuit_gate_count("add", w))
         assert oracle.circuit_gate_count("matmul", w, n) == want
+
+
+def test_full_adder_gate_count():
+    """A half adder, w - 2 full adders (two gates each) and the top sum."""
+    assert oracle.circuit_gate_count("add_fa", 1) == 1
+    for w in range(2, 40):
+        assert oracle.circuit_gate_count("add_fa", w) == 2 * w - 1

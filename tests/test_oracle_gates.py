@@ -211,3 +211,27 @@ def test_mul_tree_gate_count_equals_shift_and_add():
     for w in range(1, 40):
         want = w * (w + 1) // 2 + sum(add(w - i) for i in range(1, w))
         assert oracle.circuit_gate_count("mul_tree", w) == want == oracle.circuit_gate_count("mul", w)
+
+
+def test_three_input_gates_truth_tables(okeys):
+    """MAJ and XOR3 decrypt to majority and parity for all eight inputs, fresh
+    and on bootstrapped (noisier) inputs."""
+    combos = [(i >> 2 & 1, i >> 1 & 1, i & 1) for i in range(8)]
+    x = okeys.encrypt_bits([c[0] for c in combos], nonce=110_000)
+    y = okeys.encrypt_bits([c[1] for c in combos], nonce=111_000)
+    z = okeys.encrypt_bits([c[2] for c in combos], nonce=112_000)
+    for op, f in [(oracle.MAJ, lambda a, b, c: int(a + b + c >= 2)), (oracle.XOR3, lambda a, b, c: (a + b + c) & 1)]:
+        out = okeys.bootstrap3([op] * 8, x, y, z, threads=8)
+        assert list(okeys.decrypt_bits(out)) == [f(*c) for c in combos]
+    # inputs that are themselves gate outputs: z2 = AND(z, z) = z
+    z2 = okeys.bootstrap([oracle.AND] * 8, z, z, threads=8)
+    out = okeys.bootstrap3([oracle.XOR3] * 8, x, y, z2, threads=8)
+    assert list(okeys.decrypt_bits(out)) == [(a + b + c) & 1 for a, b, c in combos]
+
+
+def test_full_adder_circuit_decrypts_to_sum(okeys):
+    w = 5
+    a = np.array([29, 7], np.uint64)
+    b = np.array([6, 25], np.uint64)
+    R = okeys.add_fa(okeys.encrypt_uint(a, w, nonce=120_000), okeys.encrypt_uint(b, w, nonce=121_000), w)
+    np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a + b) % (1 << w))
