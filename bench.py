@@ -400,6 +400,7 @@ def main():
         dMB = F.to_device(sk.encrypt_uint(MB.reshape(-1), 16, nonce=(1 << 52) + 2048))
         dMC = torch.empty_like(dMA)
         legs = {"add16": (lambda: F.fhe_add(ctx, cA, cB, cR, 1, 16, stream), ("add", 16, 0)),
+                "add16_full_adder_gates": (lambda: F.fhe_add_fa(ctx, cA, cB, cR, 1, 16, stream), ("add_fa", 16, 0)),
                 "add16_numberwise": (lambda: F.fhe_add_numberwise(ctx, cA, cB, cR, 1, 16, stream),
                                      ("add_numberwise", 16, 0)),
                 "matmul4x4_16": (lambda: F.fhe_matmul(ctx, dMA, dMB, dMC, 4, 16, stream), ("matmul", 16, 4))}
@@ -419,6 +420,22 @@ def main():
         got = sk.decrypt_uint(F.to_host(dMC).reshape(16, 16, -1), 16).reshape(4, 4).astype(object)
         assert (got == (MA.astype(object) @ MB.astype(object)) % (1 << 16)).all()
         log(f"circuit latency: {circuits}")
+        if args.config == "add16":
+            # the benchmark's 1024 add16 pairs through full-adder gates (MAJ,
+            # XOR3): additions per second against the two-input circuit's
+            F.fhe_add_fa(ctx, dA, dB, dR, count, width, stream)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            F.fhe_add_fa(ctx, dA, dB, dR, count, width, stream)
+            torch.cuda.synchronize()
+            fa_s = time.perf_counter() - s0
+            assert (sk.decrypt_uint(F.to_host(dR), width) == (wl.operands()[0] + wl.operands()[1]) % (1 << width)).all()
+            g_fa = F.fhe_circuit_shape("add_fa", width)[0] * count
+            circuits["add16_x1024_batched"] = {
+                "two_input_gates": {"ms": round(ms_per_step, 1), "adds_per_s": round(count / (ms_per_step / 1e3), 1)},
+                "full_adder_gates": {"ms": round(1e3 * fa_s, 1), "adds_per_s": round(count / fa_s, 1),
+                                     "gates": g_fa, "gates_per_s": round(g_fa / fa_s, 1)}}
+            log(f"add16 x 1024 batched: {circuits['add16_x1024_batched']}")
 
     serving = None
     if args.serve_jobs > 0:

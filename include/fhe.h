@@ -75,10 +75,13 @@ typedef struct fhe_cloud_key fhe_cloud_key;   /* host copy of BK and KSK */
 typedef struct fhe_ctx fhe_ctx;               /* device-resident keys on one GPU */
 
 /* Gate codes, one byte each on the wire.  NY / YN negate the first / second
- * input (ANDNY = (not a) and b). */
+ * input (ANDNY = (not a) and b).  MAJ and XOR3 take three inputs (majority
+ * and parity: a full adder's carry and sum, each one bootstrap of c1 + c2 + c3
+ * resp. -2 (c1 + c2 + c3)); only fhe_bootstrap_gate3_batch and the circuits
+ * accept them. */
 typedef enum {
     FHE_AND = 0, FHE_NAND = 1, FHE_OR = 2, FHE_NOR = 3, FHE_XOR = 4, FHE_XNOR = 5,
-    FHE_ANDNY = 6, FHE_ANDYN = 7, FHE_ORNY = 8, FHE_ORYN = 9
+    FHE_ANDNY = 6, FHE_ANDYN = 7, FHE_ORNY = 8, FHE_ORYN = 9, FHE_MAJ = 10, FHE_XOR3 = 11
 } fhe_gate;
 
 /* ---------------------------------------------------------------------- */
@@ -167,6 +170,13 @@ void fhe_ctx_destroy(fhe_ctx* ctx);
 int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0,
                              const uint32_t* in1, uint32_t* out, size_t count, void* stream);
 
+/* As fhe_bootstrap_gate_batch with a third input in2 (device
+ * uint32[count][n+1]) for the three-input codes FHE_MAJ and FHE_XOR3;
+ * two-input codes ignore in2[g].  The combinations carry no constant:
+ * MAJ: c1 + c2 + c3, XOR3: -2 (c1 + c2 + c3), then the same bootstrap. */
+int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                              const uint32_t* in2, uint32_t* out, size_t count, void* stream);
+
 /* One gate per launch, synchronous: enqueues one bootstrap on `stream` and
  * waits for it.  The baseline for batched throughput. */
 int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
@@ -182,6 +192,13 @@ int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
  * A, B, R: device uint32[count][width][n+1]; width 1..64. */
 int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
             uint32_t width, void* stream);
+
+/* R = (A + B) mod 2^width by a ripple carry of full-adder gates: bit 0 a half
+ * adder (XOR, AND), then per bit r = XOR3(a, b, c) and c = MAJ(a, b, c), one
+ * level per bit: 2 width - 1 gates in width levels (16 bits: 31 gates, 16
+ * levels).  Buffers and errors as fhe_add. */
+int fhe_add_fa(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+               uint32_t width, void* stream);
 
 /* R = (A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1): w rounds
  * of carry = R & B, R = R ^ B, B = carry << 1 over all bits at once (the
@@ -284,8 +301,8 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
 
 /* Number of gates and of levels of a circuit as the library schedules it
  * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation,
- * 4 = Karatsuba, 5 = number-wise add, 6 = Cannon matmul with rows = n;
- * rows/cols only for matvec and matmul). */
+ * 4 = Karatsuba, 5 = number-wise add, 6 = Cannon matmul with rows = n,
+ * 7 = full-adder add; rows/cols only for matvec and matmul). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("FHE_LIBRARY") or os.path.join(_HERE, "libfhe_mi355x.s
 
 FHE_OK, FHE_EINVAL, FHE_ENOMEM, FHE_EDEVICE, FHE_EBUSY, FHE_ECANCELED, FHE_EIO = 0, -1, -2, -3, -4, -5, -6
 AND, NAND, OR, NOR, XOR, XNOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
+MAJ, XOR3 = 10, 11  # three-input gates (fhe_bootstrap_gate3_batch, circuits)
 WORDS = 501  # n + 1 words per LWE sample
 
 
@@ -68,6 +69,8 @@ _SIGS = {
     "fhe_mul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_mul_tree": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_add_numberwise": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_add_fa": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
+    "fhe_bootstrap_gate3_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
     "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
@@ -279,6 +282,15 @@ def fhe_add(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_add(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_add")
 
 
+def fhe_add_fa(ctx, A, B, R, count, width, stream=None):
+    _check(lib().fhe_add_fa(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)), "fhe_add_fa")
+
+
+def fhe_bootstrap_gate3_batch(ctx, ops, in0, in1, in2, out, count, stream=None):
+    _check(lib().fhe_bootstrap_gate3_batch(ctx.h, _dev(ops), _dev(in0), _dev(in1), _dev(in2), _dev(out), count,
+                                           _stream(stream)), "fhe_bootstrap_gate3_batch")
+
+
 def fhe_add_numberwise(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_add_numberwise(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)),
            "fhe_add_numberwise")
@@ -310,8 +322,9 @@ def fhe_matmul(ctx, A, B, Cm, n, width, stream=None):
 
 def fhe_circuit_shape(kind, width, rows=0, cols=0):
     """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree',
-    'karatsuba', 'add_numberwise', 'matmul'} (matmul: rows = n)."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6}[kind]
+    'karatsuba', 'add_numberwise', 'matmul', 'add_fa'} (matmul: rows = n)."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6,
+         "add_fa": 7}[kind]
     g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")

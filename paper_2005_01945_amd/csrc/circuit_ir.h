@@ -7,11 +7,14 @@
 
 namespace fhe {
 
-enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3, kKaratsuba = 4, kAddNumberwise = 5, kMatmul = 6 };
+enum Kind { kAdd = 0, kMul = 1, kMatvec = 2, kMulTree = 3, kKaratsuba = 4, kAddNumberwise = 5, kMatmul = 6, kAddFa = 7 };
+
+constexpr uint32_t kNoWire = 0xFFFFFFFFu;
 
 struct Gate {
     uint8_t op;
     uint32_t in0, in1, out;
+    uint32_t in2 = kNoWire;  // third input of FHE_MAJ / FHE_XOR3
 };
 
 // One instance of a circuit over local wire ids: [0, na) first operand,
@@ -24,7 +27,7 @@ struct Circuit {
     uint32_t wires() const { return na + nb + (uint32_t)gates.size(); }
 };
 
-// kind: kAdd / kAddNumberwise / kMul / kMulTree / kKaratsuba (operands of
+// kind: kAdd / kAddNumberwise / kAddFa / kMul / kMulTree / kKaratsuba (operands of
 // width w; Karatsuba has 2w result bits), kMatvec (rows x cols matrix of w-bit
 // entries times a cols-vector) or kMatmul (two rows x rows matrices).
 Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols);

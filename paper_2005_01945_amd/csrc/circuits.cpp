@@ -6,6 +6,9 @@
 //      bit 0:     r = a^b,            c = a&b
 //      bit i:     t = a^b, g = a&b,  r = t^c, h = t&c, c = g|h
 //      bit w-1:   t = a^b,            r = t^c      (carry out dropped)
+//  - full-adder add, sum mod 2^w: bit 0 half adder (XOR, AND); bit i
+//    r = XOR3(a, b, c), c = MAJ(a, b, c) (three-input gates, one level per
+//    bit); top bit r = XOR3(a, b, c).
 //  - number-wise add (GPU_n, Sec. V-B-1), sum mod 2^w: R = A, then w rounds
 //    of carry = R & B, R = R ^ B, B = carry << 1, each round on the bits of B
 //    not yet known zero (round k: bits k..w-1): w^2 gates in w levels.
@@ -61,10 +64,24 @@ class Builder {
         c.na = na;
         c.nb = nb;
     }
-    uint32_t gate(uint8_t op, uint32_t a, uint32_t b) {
+    uint32_t gate(uint8_t op, uint32_t a, uint32_t b, uint32_t x = kNoWire) {
         const uint32_t o = c.na + c.nb + (uint32_t)c.gates.size();
-        c.gates.push_back({op, a, b, o});
+        c.gates.push_back({op, a, b, o, x});
         return o;
+    }
+    // Ripple carry of full-adder gates: half adder, then XOR3 / MAJ per bit.
+    std::vector<uint32_t> add_fa(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+        const size_t w = a.size();
+        std::vector<uint32_t> r(w);
+        if (w == 0) return r;
+        r[0] = gate(FHE_XOR, a[0], b[0]);
+        if (w == 1) return r;
+        uint32_t carry = gate(FHE_AND, a[0], b[0]);
+        for (size_t i = 1; i < w; ++i) {
+            r[i] = gate(FHE_XOR3, a[i], b[i], carry);
+            if (i + 1 < w) carry = gate(FHE_MAJ, a[i], b[i], carry);
+        }
+        return r;
     }
     std::vector<uint32_t> add(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
         const size_t w = a.size();
@@ -305,6 +322,7 @@ Circuit build_circuit(int kind, uint32_t w, uint32_t rows, uint32_t cols) {
     const std::vector<uint32_t> a = iota_wires(0, w), b = iota_wires(w, w);
     B.c.outputs = kind == kAdd        ? B.add(a, b)
                   : kind == kAddNumberwise ? B.add_numberwise(a, b)
+                  : kind == kAddFa     ? B.add_fa(a, b)
                   : kind == kMulTree  ? B.mul_tree(a, b)
                   : kind == kKaratsuba ? B.karatsuba(a, b)
                                        : B.mul(a, b);
@@ -319,6 +337,7 @@ std::vector<uint32_t> asap_levels(const Circuit& c, uint32_t* depth) {
     for (size_t k = 0; k < c.gates.size(); ++k) {
         const Gate& g = c.gates[k];
         glev[k] = 1 + std::max(lev[g.in0], lev[g.in1]);
+        if (g.in2 != kNoWire) glev[k] = std::max(glev[k], 1 + lev[g.in2]);
         lev[g.out] = glev[k];
         d = std::max(d, glev[k]);
     }
@@ -332,6 +351,7 @@ struct Plan {
     uint64_t gates = 0;
     std::vector<uint32_t> level_off, level_width;  // into desc
     uint4* desc = nullptr;                         // device descriptors
+    uint32_t* desc3 = nullptr;                     // third-input wire ids (circuits with three-input gates)
     uint32_t* pool = nullptr;                      // intermediate samples
     uint32_t max_width = 0;
 };
@@ -383,6 +403,9 @@ int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols,
     std::vector<std::vector<uint32_t>> by_level(depth + 1);
     for (size_t k = 0; k < c.gates.size(); ++k) by_level[glev[k]].push_back((uint32_t)k);
     std::vector<uint4> desc;
+    std::vector<uint32_t> desc3;
+    bool three = false;
+    for (const Gate& g : c.gates) three |= g.in2 != kNoWire;
     desc.reserve(c.gates.size() * count);
     P->levels = depth;
     P->gates = (uint64_t)c.gates.size() * count;
@@ -392,6 +415,7 @@ int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols,
             for (uint32_t k : by_level[L]) {
                 const Gate& g = c.gates[k];
                 desc.push_back(make_uint4(g.op, gid(g.in0, inst), gid(g.in1, inst), gid(g.out, inst)));
+                if (three) desc3.push_back(g.in2 != kNoWire ? gid(g.in2, inst) : 0u);
             }
         const uint32_t wdt = (uint32_t)(desc.size() - P->level_off.back());
         P->level_width.push_back(wdt);
@@ -401,6 +425,12 @@ int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols,
     if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
     e = hipMemcpy(P->desc, desc.data(), desc.size() * sizeof(uint4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
+    if (three) {
+        e = hipMalloc((void**)&P->desc3, std::max<size_t>(desc3.size(), 1) * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
+        e = hipMemcpy(P->desc3, desc3.data(), desc3.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "circuit descriptors");
+    }
     if (npool) {
         e = hipMalloc((void**)&P->pool, (size_t)npool * count * kLweW * sizeof(uint32_t));
         if (e != hipSuccess) return hip_fail(e, "circuit pool");
@@ -410,8 +440,10 @@ int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols,
 
 void free_plan(Plan& P) {
     if (P.desc) (void)hipFree(P.desc);
+    if (P.desc3) (void)hipFree(P.desc3);
     if (P.pool) (void)hipFree(P.pool);
     P.desc = nullptr;
+    P.desc3 = nullptr;
     P.pool = nullptr;
 }
 
@@ -436,6 +468,7 @@ int get_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, s
 int enqueue_levels(fhe_ctx* ctx, const Plan* P, dev::GateIO io, hipStream_t s) {
     for (uint32_t L = 0; L < P->levels; ++L) {
         io.desc = P->desc + P->level_off[L];
+        io.desc3 = P->desc3 ? P->desc3 + P->level_off[L] : nullptr;
         int rc = run_gate_batch(ctx, io, P->level_width[L], s);
         if (rc) return rc;
     }
@@ -534,6 +567,11 @@ extern "C" int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint3
     return run_circuit(ctx, kAdd, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add");
 }
 
+extern "C" int fhe_add_fa(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                          uint32_t width, void* stream) {
+    return run_circuit(ctx, kAddFa, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add_fa");
+}
+
 extern "C" int fhe_add_numberwise(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
                                   uint32_t width, void* stream) {
     return run_circuit(ctx, kAddNumberwise, A, B, R, count, width, 0, 0, (hipStream_t)stream, "fhe_add_numberwise");
@@ -569,7 +607,7 @@ extern "C" int fhe_matmul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, ui
 
 extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,
                                  uint32_t* levels, uint64_t* widest_level) {
-    if (kind < 0 || kind > 6 || width < 1 || (kind == kKaratsuba && width < 2) || width > 64 ||
+    if (kind < 0 || kind > 7 || width < 1 || (kind == kKaratsuba && width < 2) || width > 64 ||
         (kind == kMatvec && (rows == 0 || cols == 0)) || (kind == kMatmul && (rows == 0 || rows > 64)))
         return set_error(FHE_EINVAL, "fhe_circuit_shape: bad arguments");
     const Circuit c = build_circuit(kind, width, rows, cols);

@@ -17,11 +17,13 @@ constexpr int kBlockThreads = 64 * kWavesPerBlock;
 //  Descriptor mode: desc[g] = {op, in0 wire, in1 wire, out wire}; a wire id
 //  is (region << 30) | index and addresses region[region] + index*(n+1).
 struct GateIO {
-    const uint4* desc;
+    const uint4* desc;        // {op, in0, in1, out} wire ids per gate, or null
+    const uint32_t* desc3;    // with desc: third-input wire id per gate (three-input codes), or null
     const uint8_t* ops;
     uint32_t op_const;
     const uint32_t* in0;
     const uint32_t* in1;
+    const uint32_t* in2;      // without desc: third inputs, or null
     uint32_t* out;
     uint32_t* region[4];
 };

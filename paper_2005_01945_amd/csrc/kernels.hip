@@ -740,8 +740,17 @@ struct Arith<1> {
 };
 
 // Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding).
-__device__ __forceinline__ void gate_consts(uint32_t op, uint32_t& kappa, int32_t& s1, int32_t& s2) {
+// Three-input codes (when a third input is present): no constant, all three
+// inputs with weight 1 (majority) or -2 (parity).
+__device__ __forceinline__ void gate_consts(uint32_t op, bool three, uint32_t& kappa, int32_t& s1, int32_t& s2,
+                                            int32_t& s3) {
     constexpr uint32_t mu = kMu;
+    s3 = 0;
+    if (three && (op == FHE_MAJ || op == FHE_XOR3)) {
+        kappa = 0;
+        s1 = s2 = s3 = op == FHE_MAJ ? 1 : -2;
+        return;
+    }
     switch (op) {
     case FHE_AND:   kappa = 0u - mu;      s1 = 1;  s2 = 1;  break;
     case FHE_NAND:  kappa = mu;           s1 = -1; s2 = -1; break;
@@ -760,17 +769,21 @@ __device__ __forceinline__ uint32_t* wire_ptr(const GateIO& io, uint32_t w) {
     return io.region[w >> 30] + (size_t)(w & 0x3FFFFFFFu) * NW;
 }
 
+// c3 is null for a two-input gate.
 __device__ __forceinline__ void gate_operands(const GateIO& io, uint32_t g, uint32_t& op,
-                                              const uint32_t*& c1, const uint32_t*& c2) {
+                                              const uint32_t*& c1, const uint32_t*& c2, const uint32_t*& c3) {
+    c3 = nullptr;
     if (io.desc) {
         const uint4 d = io.desc[g];
         op = d.x;
         c1 = wire_ptr(io, d.y);
         c2 = wire_ptr(io, d.z);
+        if (io.desc3 && (op == FHE_MAJ || op == FHE_XOR3)) c3 = wire_ptr(io, io.desc3[g]);
     } else {
         op = io.ops ? io.ops[g] : io.op_const;
         c1 = io.in0 + (size_t)g * NW;
         c2 = io.in1 + (size_t)g * NW;
+        if (io.in2 && (op == FHE_MAJ || op == FHE_XOR3)) c3 = io.in2 + (size_t)g * NW;
     }
 }
 
@@ -791,17 +804,18 @@ __device__ __forceinline__ void load_twiddles(L& S, const uint64_t* twf, const u
 // words l + 64k in ab[k]; returns bbar (uniform).
 __device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int lane, uint32_t (&ab)[8]) {
     uint32_t op;
-    const uint32_t *c1, *c2;
-    gate_operands(io, g, op, c1, c2);
+    const uint32_t *c1, *c2, *c3;
+    gate_operands(io, g, op, c1, c2, c3);
     uint32_t kappa;
-    int32_t s1, s2;
-    gate_consts(op, kappa, s1, s2);
+    int32_t s1, s2, s3;
+    gate_consts(op, c3 != nullptr, kappa, s1, s2, s3);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int w = lane + 64 * k;
         uint32_t v = 0;
         if (w < NW) {
             v = (uint32_t)s1 * c1[w] + (uint32_t)s2 * c2[w];
+            if (c3) v += (uint32_t)s3 * c3[w];
             if (w == NLWE) v += kappa;
         }
         ab[k] = (v + (1u << 20)) >> 21;

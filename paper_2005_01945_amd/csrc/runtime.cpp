@@ -271,6 +271,22 @@ extern "C" int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const 
     return run_gate_batch(ctx, io, count, (hipStream_t)stream);
 }
 
+extern "C" int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                                         const uint32_t* in2, uint32_t* out, size_t count, void* stream) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_gate3_batch: null context");
+    if (count == 0) return FHE_OK;
+    if (!ops || !in0 || !in1 || !in2 || !out) return set_error(FHE_EINVAL, "fhe_bootstrap_gate3_batch: null buffer");
+    if (count > (size_t)1 << 30) return set_error(FHE_EINVAL, "fhe_bootstrap_gate3_batch: count %zu too large", count);
+    DeviceGuard guard(ctx->device);
+    dev::GateIO io{};
+    io.ops = ops;
+    io.in0 = in0;
+    io.in1 = in1;
+    io.in2 = in2;
+    io.out = out;
+    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+}
+
 extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
                                         const uint32_t* in1, uint32_t* out, void* stream) {
     if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_plain: null context");

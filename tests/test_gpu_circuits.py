@@ -60,6 +60,20 @@ def test_add_numberwise_bit_exact(env, width, count):
     np.testing.assert_array_equal(got, K.add_numberwise(ca, cb, width))
 
 
+@pytest.mark.parametrize("width,count", [(1, 2), (4, 3), (16, 2)])
+def test_add_fa_bit_exact(env, width, count):
+    """Full-adder gates (MAJ, XOR3): one level per bit."""
+    sk, ctx, K = env
+    a = workloads.uniform_uints(130 + width, count, width)
+    b = workloads.uniform_uints(140 + width, count, width)
+    ca = sk.encrypt_uint(a, width, nonce=2_300_000)
+    cb = sk.encrypt_uint(b, width, nonce=2_400_000)
+    log(f"add_fa width={width} count={count}")
+    got = gpu_binary(ctx, F.fhe_add_fa, ca, cb, count, width)
+    np.testing.assert_array_equal(sk.decrypt_uint(got, width), (a + b) % (1 << width))
+    np.testing.assert_array_equal(got, K.add_fa(ca, cb, width))
+
+
 @pytest.mark.parametrize("width,count", [(1, 1), (3, 2), (5, 2)])
 def test_mul_bit_exact(env, width, count):
     sk, ctx, K = env

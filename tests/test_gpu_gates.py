@@ -197,3 +197,28 @@ def test_wide_ragged_batch_sampled_bit_exact(env):
     pick = np.array([0, 1, 8191, 16383, 16384])
     log("oracle: 5 sampled gates")
     np.testing.assert_array_equal(got[pick], K.bootstrap(ops[pick], c0[pick], c1[pick], threads=5))
+
+
+def test_three_input_gates_bit_exact(env):
+    """MAJ and XOR3 on all eight input combinations, and two-input codes
+    through the three-input entry point (third input ignored), against the
+    oracle; inputs include gate outputs."""
+    import torch
+    sk, ctx, K = env[0], env[1], env[2]
+    combos = [(i >> 2 & 1, i >> 1 & 1, i & 1) for i in range(8)]
+    x = sk.encrypt_bits([c[0] for c in combos] * 3, nonce=6_000_000)
+    y = sk.encrypt_bits([c[1] for c in combos] * 3, nonce=6_100_000)
+    z = K.bootstrap([F.AND] * 24, sk.encrypt_bits([c[2] for c in combos] * 3, nonce=6_200_000),
+                    sk.encrypt_bits([1] * 24, nonce=6_300_000), threads=8)
+    ops = np.array([F.MAJ] * 8 + [F.XOR3] * 8 + [F.NAND] * 8, np.uint8)
+    d_ops = torch.from_numpy(ops).cuda()
+    d = [F.to_device(v) for v in (x, y, z)]
+    out = torch.empty_like(d[0])
+    log("three-input gates x 24")
+    F.fhe_bootstrap_gate3_batch(ctx, d_ops, d[0], d[1], d[2], out, 24)
+    torch.cuda.synchronize()
+    got = F.to_host(out)
+    want_bits = [int(a + b + c >= 2) for a, b, c in combos] + [(a + b + c) & 1 for a, b, c in combos] + \
+        [1 - (a & b) for a, b, c in combos]
+    assert list(sk.decrypt_bits(got)) == want_bits
+    np.testing.assert_array_equal(got, K.bootstrap3(ops, x, y, z, threads=8))

@@ -110,6 +110,7 @@ def test_argument_errors():
     L = F.lib()
     assert L.fhe_bootstrap_gate_batch(None, None, None, None, None, 4, None) == F.FHE_EINVAL
     assert L.fhe_add(None, None, None, None, 1, 8, None) == F.FHE_EINVAL
+    assert L.fhe_bootstrap_gate3_batch(None, None, None, None, None, None, 4, None) == F.FHE_EINVAL
     assert b"null context" in L.fhe_last_error()
     assert L.fhe_debug_cmux(0, 0, None, 0, None) == F.FHE_EINVAL
     assert L.fhe_debug_cmux(0, 2, None, 0, None) == F.FHE_EINVAL
@@ -126,6 +127,9 @@ def test_circuit_shapes_match_oracle_gate_counts():
     assert F.fhe_circuit_shape("add_numberwise", 16) == (256, 16, 31)
     for n, w in [(1, 3), (2, 16), (3, 5), (4, 16)]:
         assert F.fhe_circuit_shape("matmul", w, n)[0] == oracle.circuit_gate_count("matmul", w, n)
+    for w in (1, 2, 5, 16, 32):
+        assert F.fhe_circuit_shape("add_fa", w)[0] == oracle.circuit_gate_count("add_fa", w)
+    assert F.fhe_circuit_shape("add_fa", 16) == (31, 16, 2)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64)[0] == oracle.circuit_gate_count("matvec", 16, 64, 64)
     assert F.fhe_circuit_shape("matvec", 3, 5, 7)[0] == oracle.circuit_gate_count("matvec", 3, 5, 7)
     # gates, ASAP depth, widest level of the paper-sized circuits
