@@ -306,6 +306,16 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 
+/* The level schedule the circuit calls run for `count` instances on a device
+ * with cu_count compute units (host only): level_gates[L] = gates in launch
+ * L (max_levels entries available), *levels = number of launches.  Levels
+ * start from ASAP; a level narrower than one round of the widest launch shape
+ * (8 cu_count gates) takes gates with slack from earlier levels (each still
+ * after its inputs and before its consumers) when a per-round cost model says
+ * the whole schedule gets faster.  The gates and the depth do not change. */
+int fhe_circuit_schedule(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t count,
+                         uint32_t cu_count, uint64_t* level_gates, uint32_t max_levels, uint32_t* levels);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of jobs on one context.                     */
 /* A worker thread owns the context while the server exists (no other call */

@@ -74,6 +74,8 @@ _SIGS = {
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
     "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
+    "fhe_circuit_schedule": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32,
+                                       C.POINTER(C.c_uint64), C.c_uint32, C.POINTER(C.c_uint32)]),
     "fhe_circuit_shape": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
     "fhe_ctx_set_timing": (C.c_int, [_vp, C.c_int]),
@@ -318,6 +320,19 @@ def fhe_matvec(ctx, M, x, y, rows, cols, width, stream=None):
 def fhe_matmul(ctx, A, B, Cm, n, width, stream=None):
     """C = A B mod 2^width (n x n) by Cannon's algorithm."""
     _check(lib().fhe_matmul(ctx.h, _dev(A), _dev(B), _dev(Cm), n, width, _stream(stream)), "fhe_matmul")
+
+
+def fhe_circuit_schedule(kind, width, count, cu_count=256, rows=0, cols=0):
+    """Gates per launch of the level schedule for `count` instances."""
+    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6,
+         "add_fa": 7}[kind]
+    lv = C.c_uint32()
+    _check(lib().fhe_circuit_schedule(k, width, rows, cols, count, cu_count, None, 0, C.byref(lv)),
+           "fhe_circuit_schedule")
+    out = (C.c_uint64 * max(lv.value, 1))()
+    _check(lib().fhe_circuit_schedule(k, width, rows, cols, count, cu_count, out, lv.value, C.byref(lv)),
+           "fhe_circuit_schedule")
+    return [out[i] for i in range(lv.value)]
 
 
 def fhe_circuit_shape(kind, width, rows=0, cols=0):

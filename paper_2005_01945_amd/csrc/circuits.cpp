@@ -345,7 +345,70 @@ std::vector<uint32_t> asap_levels(const Circuit& c, uint32_t* depth) {
     return glev;
 }
 
-// A scheduled, device-resident plan for (kind, width, rows, cols, count).
+// Relative time of one launch of `gates` gates, in units of one round of the
+// widest launch shape (`round` gates: eight per compute unit, two waves per
+// SIMD), from the measured shape timings: a level of at most an eighth, a
+// quarter or half a round runs on the narrower shapes in about 0.27, 0.36 and
+// 0.64 of a round's time; wider levels take whole rounds.
+static double level_cost(uint64_t gates, uint64_t round) {
+    if (gates == 0) return 0.0;
+    if (8 * gates <= round) return 0.27;
+    if (4 * gates <= round) return 0.36;
+    if (2 * gates <= round) return 0.64;
+    return (double)((gates + round - 1) / round);
+}
+
+// Level balancing: ASAP levels put every gate whose inputs are ready at the
+// earliest level (e.g. all partial products and operand XORs/ANDs at level
+// 1), leaving the levels along the critical path narrow.  A gate with slack
+// can run at any level between its ASAP level and its latest level (ALAP)
+// as long as its inputs come from earlier levels and its consumers run
+// later.  Levels (ascending) narrower than one round take the most urgent
+// such gates until they hold one round; the result is kept only if the cost
+// model above says it is faster.  The depth and every gate's inputs and
+// outputs are unchanged, so the words computed are too.
+static std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_t>& asap, uint32_t depth,
+                                            size_t count, uint64_t round) {
+    const size_t ng = c.gates.size();
+    const uint32_t base = c.na + c.nb;
+    std::vector<std::vector<uint32_t>> cons(ng);
+    for (size_t k = 0; k < ng; ++k) {
+        const Gate& g = c.gates[k];
+        for (uint32_t w : {g.in0, g.in1, g.in2})
+            if (w != kNoWire && w >= base) cons[w - base].push_back((uint32_t)k);
+    }
+    std::vector<uint32_t> alap(ng, depth);
+    for (size_t k = ng; k-- > 0;)
+        for (uint32_t q : cons[k]) alap[k] = std::min(alap[k], alap[q] - 1);
+    std::vector<uint32_t> slack;
+    for (size_t k = 0; k < ng; ++k)
+        if (alap[k] > asap[k]) slack.push_back((uint32_t)k);
+    std::stable_sort(slack.begin(), slack.end(), [&](uint32_t a, uint32_t b) { return alap[a] < alap[b]; });
+    std::vector<uint32_t> lev(asap);
+    std::vector<uint64_t> width(depth + 1, 0);
+    for (uint32_t l : lev) width[l]++;
+    const std::vector<uint64_t> width0(width);
+    for (uint32_t L = 2; L <= depth; ++L) {
+        for (uint32_t k : slack) {
+            if ((width[L] + 1) * count > round) break;
+            if (lev[k] >= L || alap[k] < L) continue;
+            bool ok = true;
+            for (uint32_t q : cons[k]) ok = ok && lev[q] > L;
+            if (!ok) continue;
+            width[lev[k]]--;
+            width[L]++;
+            lev[k] = L;
+        }
+    }
+    double before = 0, after = 0;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        before += level_cost(width0[L] * count, round);
+        after += level_cost(width[L] * count, round);
+    }
+    return after < before ? lev : asap;
+}
+
+// A scheduled, device-resident plan for (kind, width, rows, cols, count).// A scheduled, device-resident plan for (kind, width, rows, cols, count).
 struct Plan {
     uint32_t levels = 0;
     uint64_t gates = 0;
@@ -381,7 +444,8 @@ uint32_t wire_id(uint32_t region, uint64_t index) { return (region << 30) | (uin
 int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, size_t count, Plan* P) {
     const Circuit c = build_circuit(kind, w, rows, cols);
     uint32_t depth = 0;
-    const std::vector<uint32_t> glev = asap_levels(c, &depth);
+    const std::vector<uint32_t> asap = asap_levels(c, &depth);
+    const std::vector<uint32_t> glev = balance_levels(c, asap, depth, count, 8 * (uint64_t)ctx->cu_count);
     const uint32_t nw = c.wires();
     // Local wire -> (region, index within instance) for one instance.
     std::vector<uint32_t> region(nw, kRegionPool), local(nw, 0);
@@ -603,6 +667,25 @@ extern "C" int fhe_matmul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, ui
                           uint32_t width, void* stream) {
     if (n == 0 || n > 64) return set_error(FHE_EINVAL, "fhe_matmul: dimension %u not in 1..64", n);
     return run_circuit(ctx, kMatmul, A, B, C, 1, width, n, 0, (hipStream_t)stream, "fhe_matmul");
+}
+
+extern "C" int fhe_circuit_schedule(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t count,
+                                    uint32_t cu_count, uint64_t* level_gates, uint32_t max_levels, uint32_t* levels) {
+    if (kind < 0 || kind > 7 || width < 1 || width > 64 || count == 0 || count > (1ull << 30) || cu_count == 0 ||
+        (kind == kKaratsuba && width < 2) || (kind == kMatvec && (rows == 0 || cols == 0)) ||
+        (kind == kMatmul && (rows == 0 || rows > 64)))
+        return set_error(FHE_EINVAL, "fhe_circuit_schedule: bad arguments");
+    const Circuit c = build_circuit(kind, width, rows, cols);
+    uint32_t depth = 0;
+    const std::vector<uint32_t> asap = asap_levels(c, &depth);
+    const std::vector<uint32_t> lev = balance_levels(c, asap, depth, count, 8 * (uint64_t)cu_count);
+    if (levels) *levels = depth;
+    if (level_gates) {
+        if (max_levels < depth) return set_error(FHE_EINVAL, "fhe_circuit_schedule: %u levels do not fit", depth);
+        for (uint32_t L = 0; L < depth; ++L) level_gates[L] = 0;
+        for (uint32_t l : lev) level_gates[l - 1] += count;
+    }
+    return FHE_OK;
 }
 
 extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t* gates,

@@ -141,3 +141,20 @@ def test_circuit_shapes_match_oracle_gate_counts():
     assert F.fhe_circuit_shape("karatsuba", 32)[:2] == (5271, 116)
     assert F.fhe_circuit_shape("karatsuba", 16)[:2] == (1457, 58)
     assert F.fhe_circuit_shape("matvec", 16, 64, 64) == (2952576, 68, 557056)
+
+
+def test_level_schedule_balancing():
+    """add16 x 1024 on 256 compute units: ASAP puts 31,744 gates at level 1
+    and alternates 2,048 / 1,024 after; balancing moves operand XOR/ANDs with
+    slack into the narrow levels so that every level after the first holds one
+    round of 2,048 gates (37 rounds instead of 45.5).  Same gates, same
+    depth."""
+    sched = F.fhe_circuit_schedule("add", 16, 1024)
+    assert len(sched) == 30 and sum(sched) == 74 * 1024
+    assert sched == [16384] + [2048] * 29
+    # one instance: every level is narrow either way, nothing moves
+    assert F.fhe_circuit_schedule("add", 16, 1) == [31] + [2, 1] * 14 + [1]
+    for kind, w, n in [("mul", 32, 256), ("mul_tree", 32, 256), ("add_fa", 16, 1024), ("karatsuba", 32, 64)]:
+        sched = F.fhe_circuit_schedule(kind, w, n)
+        gates, depth, _ = F.fhe_circuit_shape(kind, w)
+        assert len(sched) == depth and sum(sched) == gates * n
