@@ -166,7 +166,10 @@ void fhe_ctx_destroy(fhe_ctx* ctx);
  * vector, sample extraction and key switching, all gates of the batch in one
  * launch per step.  ops: device uint8[count]; in0, in1, out: device
  * uint32[count][n+1].  count = 0 is a no-op.  The result is bit-exact with
- * the definition (exact NTT arithmetic). */
+ * the definition (exact NTT arithmetic).  The codes live in device memory and
+ * are not checked on the host: a code outside FHE_AND..FHE_ORYN (including
+ * the three-input codes, which need fhe_bootstrap_gate3_batch) computes
+ * FHE_ORYN. */
 int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0,
                              const uint32_t* in1, uint32_t* out, size_t count, void* stream);
 
