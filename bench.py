@@ -190,8 +190,8 @@ def main():
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path shards by independent gates, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the gates of a level are "
+              "independent, so several GPUs would each take a share of every level", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -54,9 +54,8 @@ enum {
 };
 
 /* TFHE parameters.  The library's kernels are specialised for the 110-bit
- * gate-bootstrapping set the paper uses (Sec. VII: "analogous to the
- * existing implementation of TFHE"): n=500, N=1024, k=1, l=2, Bgbit=10, t=8,
- * basebit=2.  Any other structural value is rejected with FHE_EINVAL; the
+ * gate-bootstrapping set the paper uses (Sec. VII: the parameters of the TFHE
+ * library): n=500, N=1024, k=1, l=2, Bgbit=10, t=8, basebit=2.  Any other structural value is rejected with FHE_EINVAL; the
  * noise deviations may be changed (0 gives noiseless keys for tests). */
 typedef struct {
     uint32_t n;          /* LWE dimension */
