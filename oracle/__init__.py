@@ -75,6 +75,7 @@ def lib():
             "or_gate_combine": (None, [PP, C.c_int, u32p, u32p, u32p]),
             "or_external_product_cmux": (None, [PP, u32p, C.c_int32, u32p]),
             "or_blind_rotate": (None, [KP, u32p, u32p]),
+            "or_blind_rotate_tv": (None, [KP, u32p, u32p, u32p]),
             "or_sample_extract": (None, [PP, u32p, u32p]),
             "or_key_switch": (None, [KP, u32p, u32p]),
             "or_bootstrap_gate": (None, [KP, C.c_int, u32p, u32p, u32p]),
@@ -86,6 +87,7 @@ def lib():
             "or_circuit_add_numberwise": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_matmul": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_add_fa": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_bootstrap_lut": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_bootstrap_gates3": (None, [KP, u8p, u32p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
             "or_circuit_matvec": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int32, C.c_int]),
@@ -195,10 +197,16 @@ class Keys:
         return (bits << np.arange(width, dtype=np.uint64)[None, :]).sum(axis=1, dtype=np.uint64)
 
     # --- bootstrapping pieces ---
-    def blind_rotate(self, lwe_in) -> np.ndarray:
+    def blind_rotate(self, lwe_in, tv=None) -> np.ndarray:
+        """Blind rotation of the gate test vector (mu everywhere) or of tv[N]."""
         x = _c(lwe_in, np.uint32)
         acc = np.empty(2 * self.P.N, np.uint32)
-        lib().or_blind_rotate(self.ref(), _u32p(x), _u32p(acc))
+        if tv is None:
+            lib().or_blind_rotate(self.ref(), _u32p(x), _u32p(acc))
+        else:
+            v = _c(tv, np.uint32)
+            assert v.size == self.P.N
+            lib().or_blind_rotate_tv(self.ref(), _u32p(x), _u32p(v), _u32p(acc))
         return acc.reshape(2, self.P.N)
 
     def sample_extract(self, acc) -> np.ndarray:
@@ -245,6 +253,14 @@ class Keys:
         b = _c(B, np.uint32).reshape(-1, width, self.width)
         out = np.empty_like(a)
         lib().or_circuit_mul_tree(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
+    def bootstrap_lut(self, tv, ct, threads: int = 0) -> np.ndarray:
+        """Programmable bootstrapping of samples ct [count][n+1] with test vector tv[N]."""
+        v = _c(tv, np.uint32)
+        c = _c(ct, np.uint32).reshape(-1, self.width)
+        out = np.empty_like(c)
+        lib().or_bootstrap_lut(self.ref(), _u32p(v), _u32p(c), _u32p(out), c.shape[0], threads)
         return out
 
     def add_fa(self, A, B, width: int, threads: int = 0) -> np.ndarray:

@@ -333,18 +333,28 @@ void or_external_product_cmux(const or_params* P, const uint32_t* bk_i,
 /* Blind rotation of the test vector v = sum_j mu X^j:
  *   acc = (0, X^(2N - bbar) v);  for i < n: CMux with BK_i and abar_i.
  * lwe_in is the gate's combined sample (n+1 words). */
-void or_blind_rotate(const or_keys* K, const uint32_t* lwe_in, uint32_t* acc) {
+/* Blind rotation of test vector tv (N words): ACC = (0, X^(2N - bbar) tv),
+ * then the n CMux steps.  Coefficient 0 of the result's body polynomial
+ * encrypts tv[phibar] for a modulus-switched phase phibar < N and
+ * -tv[phibar - N] above. */
+void or_blind_rotate_tv(const or_keys* K, const uint32_t* lwe_in, const uint32_t* tv, uint32_t* acc) {
     const or_params* P = &K->P;
     const int32_t n = P->n, N = P->N, L2 = 2 * P->bk_l;
-    uint32_t* v = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
-    for (int32_t j = 0; j < N; j++) v[j] = OR_MU;
     int32_t bbar = (int32_t)or_modswitch(P, lwe_in[n]);
     memset(acc, 0, (size_t)N * sizeof(uint32_t));
-    or_rotate(N, v, 2 * N - bbar, acc + N);
+    or_rotate(N, tv, 2 * N - bbar, acc + N);
     for (int32_t i = 0; i < n; i++) {
         int32_t abar = (int32_t)or_modswitch(P, lwe_in[i]);
         or_external_product_cmux(P, K->bk + (size_t)i * L2 * 2 * N, abar, acc);
     }
+}
+
+/* Gate bootstrapping's test vector: mu in every coefficient. */
+void or_blind_rotate(const or_keys* K, const uint32_t* lwe_in, uint32_t* acc) {
+    const int32_t N = K->P.N;
+    uint32_t* v = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+    for (int32_t j = 0; j < N; j++) v[j] = OR_MU;
+    or_blind_rotate_tv(K, lwe_in, v, acc);
     free(v);
 }
 
@@ -402,6 +412,60 @@ void or_bootstrap_gate3(const or_keys* K, int op, const uint32_t* c1, const uint
     free(comb);
     free(acc);
     free(big);
+}
+
+/* Programmable bootstrapping: no gate combination, the input's own phase
+ * selects the test-vector entry; blind rotation of tv, sample extraction, key
+ * switching.  count samples [count][n+1], independent, on `threads`. */
+typedef struct {
+    const or_keys* K;
+    const uint32_t* tv;
+    const uint32_t* in;
+    uint32_t* out;
+    size_t count, next;
+    pthread_mutex_t lock;
+} lut_job;
+
+static void* lut_worker(void* arg) {
+    lut_job* J = (lut_job*)arg;
+    const or_params* P = &J->K->P;
+    const size_t W = (size_t)P->n + 1;
+    uint32_t* acc = (uint32_t*)malloc(2u * (size_t)P->N * sizeof(uint32_t));
+    uint32_t* big = (uint32_t*)malloc((size_t)(P->N + 1) * sizeof(uint32_t));
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        size_t g = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (g >= J->count) break;
+        or_blind_rotate_tv(J->K, J->in + g * W, J->tv, acc);
+        or_sample_extract(P, acc, big);
+        or_key_switch(J->K, big, J->out + g * W);
+    }
+    free(acc);
+    free(big);
+    return NULL;
+}
+
+static int resolve_threads(int threads);
+
+void or_bootstrap_lut(const or_keys* K, const uint32_t* tv, const uint32_t* in, uint32_t* out, size_t count,
+                      int threads) {
+    if (count == 0) return;
+    lut_job J;
+    J.K = K;
+    J.tv = tv;
+    J.in = in;
+    J.out = out;
+    J.count = count;
+    J.next = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    int T = resolve_threads(threads);
+    if ((size_t)T > count) T = (int)count;
+    pthread_t* tid = (pthread_t*)malloc((size_t)T * sizeof(pthread_t));
+    for (int i = 0; i < T; i++) pthread_create(&tid[i], NULL, lut_worker, &J);
+    for (int i = 0; i < T; i++) pthread_join(tid[i], NULL);
+    free(tid);
+    pthread_mutex_destroy(&J.lock);
 }
 
 void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,

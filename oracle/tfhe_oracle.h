@@ -98,6 +98,13 @@ void or_gate_combine(const or_params* P, int op, const uint32_t* c1,
 void or_external_product_cmux(const or_params* P, const uint32_t* bk_i,
                               int32_t abar, uint32_t* acc);
 void or_blind_rotate(const or_keys* K, const uint32_t* lwe_in, uint32_t* acc);
+/* Blind rotation of an arbitrary test vector tv[N] (programmable bootstrapping). */
+void or_blind_rotate_tv(const or_keys* K, const uint32_t* lwe_in, const uint32_t* tv, uint32_t* acc);
+/* out[g] = key switch of the sample extracted from the blind rotation of tv
+ * by in[g] (no gate combination): encrypts tv[phibar] for phibar < N and
+ * -tv[phibar - N] above, phibar the modulus-switched phase of in[g]. */
+void or_bootstrap_lut(const or_keys* K, const uint32_t* tv, const uint32_t* in, uint32_t* out, size_t count,
+                      int threads);
 void or_sample_extract(const or_params* P, const uint32_t* acc, uint32_t* lwe_big);
 void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out);
 

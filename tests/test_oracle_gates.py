@@ -235,3 +235,45 @@ def test_full_adder_circuit_decrypts_to_sum(okeys):
     b = np.array([6, 25], np.uint64)
     R = okeys.add_fa(okeys.encrypt_uint(a, w, nonce=120_000), okeys.encrypt_uint(b, w, nonce=121_000), w)
     np.testing.assert_array_equal(okeys.decrypt_uint(R, w), (a + b) % (1 << w))
+
+
+def lut_encrypt(K, phases, seed):
+    """Noiseless LWE samples of the given torus phases (uint32) under K's key."""
+    g = np.random.default_rng(seed)
+    n = K.P.n
+    a = g.integers(0, M32, (len(phases), n), dtype=np.uint64)
+    b = ((a * K.lwe_key.astype(np.uint64)).sum(axis=1) + np.asarray(phases, np.uint64)) % M32
+    return np.concatenate([a, b[:, None]], axis=1).astype(np.uint32)
+
+
+def test_lut_zero_key_closed_form():
+    """Programmable bootstrapping with s = 0 and noiseless keys: the extracted
+    phase is exactly tv[bbar] for bbar < N and -tv[bbar - N] above."""
+    P = oracle.default_params(lwe_stdev=0.0, bk_stdev=0.0)
+    K = oracle.Keys(seed=3, params=P, lwe_key=np.zeros(P.n, np.int32))
+    g = np.random.default_rng(6)
+    tv = g.integers(0, M32, P.N, dtype=np.uint64).astype(np.uint32)
+    for trial in range(4):
+        lwe = g.integers(0, M32, P.n + 1, dtype=np.uint64).astype(np.uint32)
+        big = K.sample_extract(K.blind_rotate(lwe, tv))
+        S = K.tlwe_key.astype(np.int64)
+        ph = (int(big[-1]) - int((big[:-1].astype(np.int64) * S).sum())) % M32
+        bbar = oracle.modswitch(int(lwe[-1]), P)
+        assert ph == (int(tv[bbar]) if bbar < P.N else (M32 - int(tv[bbar - P.N])) % M32)
+    # the constant vector mu is the gate test vector
+    lwe = g.integers(0, M32, P.n + 1, dtype=np.uint64).astype(np.uint32)
+    np.testing.assert_array_equal(K.blind_rotate(lwe, np.full(P.N, MU, np.uint32)), K.blind_rotate(lwe))
+
+
+def test_lut_two_bit_function(okeys):
+    """A 2-bit lookup table with a padding bit: m in {0..3} at phase m/8 + 1/16
+    (so the phase stays in [0, 1/2)); tv holds f(m)/8 + 1/16 on the quarter of
+    [0, N) that m's phase switches to; the output decrypts to f(m)."""
+    N = okeys.P.N
+    f = [3, 0, 2, 1]
+    tv = np.array([(f[j * 4 // N] << 29) + (1 << 28) for j in range(N)], np.uint32)
+    ms = np.array([0, 1, 2, 3, 3, 2, 1, 0])
+    ct = lut_encrypt(okeys, (ms << 29) + (1 << 28), seed=7)
+    out = okeys.bootstrap_lut(tv, ct, threads=8)
+    ph = okeys.phase(out).astype(np.int64) % M32
+    assert list((ph >> 29) & 3) == [f[m] for m in ms]
