@@ -179,6 +179,16 @@ int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* i
 int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
                               const uint32_t* in2, uint32_t* out, size_t count, void* stream);
 
+/* Programmable bootstrapping: out[g] = the bootstrapped and key-switched
+ * sample of in[g] with the test vector tv (device uint32[N]) in place of the
+ * gates' constant one; no gate combination.  For the modulus-switched phase
+ * phibar = round(2N phase(in[g])) mod 2N, out[g] encrypts tv[phibar] when
+ * phibar < N and -tv[phibar - N] otherwise (a negacyclic lookup table; keep
+ * inputs in [0, 1/2) with a padding bit for an arbitrary function).  in, out:
+ * device uint32[count][n+1].  Bit-exact with the definition like the gates. */
+int fhe_bootstrap_lut_batch(fhe_ctx* ctx, const uint32_t* tv, const uint32_t* in, uint32_t* out,
+                            size_t count, void* stream);
+
 /* One gate per launch, synchronous: enqueues one bootstrap on `stream` and
  * waits for it.  The baseline for batched throughput. */
 int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,

@@ -71,6 +71,7 @@ _SIGS = {
     "fhe_add_numberwise": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_add_fa": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_bootstrap_gate3_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_bootstrap_lut_batch": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
     "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
@@ -291,6 +292,12 @@ def fhe_add_fa(ctx, A, B, R, count, width, stream=None):
 def fhe_bootstrap_gate3_batch(ctx, ops, in0, in1, in2, out, count, stream=None):
     _check(lib().fhe_bootstrap_gate3_batch(ctx.h, _dev(ops), _dev(in0), _dev(in1), _dev(in2), _dev(out), count,
                                            _stream(stream)), "fhe_bootstrap_gate3_batch")
+
+
+def fhe_bootstrap_lut_batch(ctx, tv, inp, out, count, stream=None):
+    """Programmable bootstrapping with test vector tv (device uint32[N])."""
+    _check(lib().fhe_bootstrap_lut_batch(ctx.h, _dev(tv), _dev(inp), _dev(out), count, _stream(stream)),
+           "fhe_bootstrap_lut_batch")
 
 
 def fhe_add_numberwise(ctx, A, B, R, count, width, stream=None):

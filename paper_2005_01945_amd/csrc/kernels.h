@@ -24,6 +24,7 @@ struct GateIO {
     const uint32_t* in0;
     const uint32_t* in1;
     const uint32_t* in2;      // without desc: third inputs, or null
+    const uint32_t* tv;       // programmable bootstrapping: test vector [N] (in0 taken as is), or null
     uint32_t* out;
     uint32_t* region[4];
 };

@@ -809,6 +809,13 @@ __device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int l
     uint32_t kappa;
     int32_t s1, s2, s3;
     gate_consts(op, c3 != nullptr, kappa, s1, s2, s3);
+    if (io.tv) {  // programmable bootstrapping: the input sample itself
+        s1 = 1;
+        s2 = s3 = 0;
+        kappa = 0;
+        c2 = c1;
+        c3 = nullptr;
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int w = lane + 64 * k;
@@ -825,8 +832,21 @@ __device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int l
 
 // Test-vector rotation: ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... +
 // X^(N-1)).  Lane l = 32h + t writes coefficients t + 32q of polynomial h.
-__device__ __forceinline__ void acc_init(uint32_t (&acc)[2][1024], int bbar, int h, int t) {
+// With a test vector tv (programmable bootstrapping): ACC = (0, X^c tv),
+// coefficient m = tv[j] for j = (m - c) mod 2N < N, else -tv[j - N].
+__device__ __forceinline__ void acc_init(uint32_t (&acc)[2][1024], int bbar, int h, int t,
+                                         const uint32_t* __restrict__ tv) {
     const int c = (2 * N - bbar) & (2 * N - 1);
+    if (tv) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int m = t + 32 * q;
+            const int j = (m - c) & (2 * N - 1);
+            const uint32_t v = tv[j & (N - 1)];
+            acc[h][m] = h == 0 ? 0u : (j < N ? v : 0u - v);
+        }
+        return;
+    }
     const int cm = c & (N - 1);
     const uint32_t neg = (c >= N) ? 1u : 0u;
 #pragma unroll
@@ -870,7 +890,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
     auto& W = S.w[wave];
-    acc_init(W.acc, bbar, h, t);
+    acc_init(W.acc, bbar, h, t, io.tv);
     wave_lds_sync();
 
     // Blind rotation.  abar_i = 0 would give D = 0 and leave ACC unchanged,
@@ -907,7 +927,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    if (wave == 0) acc_init(S.acc, bbar, h, t);
+    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv);
     __syncthreads();
 
     const uint64_t* bk = Arith<A>::bk(K);
@@ -1032,7 +1052,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    if (wave == 0) acc_init(S.acc, bbar, h, t);
+    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv);
     __syncthreads();
 
     const int32_t* twf = reinterpret_cast<const int32_t*>(S.twf);

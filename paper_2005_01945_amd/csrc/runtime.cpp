@@ -287,6 +287,22 @@ extern "C" int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const
     return run_gate_batch(ctx, io, count, (hipStream_t)stream);
 }
 
+extern "C" int fhe_bootstrap_lut_batch(fhe_ctx* ctx, const uint32_t* tv, const uint32_t* in, uint32_t* out,
+                                       size_t count, void* stream) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_lut_batch: null context");
+    if (count == 0) return FHE_OK;
+    if (!tv || !in || !out) return set_error(FHE_EINVAL, "fhe_bootstrap_lut_batch: null buffer");
+    if (count > (size_t)1 << 30) return set_error(FHE_EINVAL, "fhe_bootstrap_lut_batch: count %zu too large", count);
+    DeviceGuard guard(ctx->device);
+    dev::GateIO io{};
+    io.op_const = FHE_AND;  // (no combination: the sample itself is rotated)
+    io.in0 = in;
+    io.in1 = in;
+    io.tv = tv;
+    io.out = out;
+    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+}
+
 extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
                                         const uint32_t* in1, uint32_t* out, void* stream) {
     if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_gate_plain: null context");

@@ -222,3 +222,41 @@ def test_three_input_gates_bit_exact(env):
         [1 - (a & b) for a, b, c in combos]
     assert list(sk.decrypt_bits(got)) == want_bits
     np.testing.assert_array_equal(got, K.bootstrap3(ops, x, y, z, threads=8))
+
+
+def test_programmable_bootstrap_bit_exact(env):
+    """Programmable bootstrapping with a random test vector on encryptions of
+    random phases (every launch shape's prologue path), and a 2-bit lookup
+    table that decrypts to f(m), against the oracle."""
+    import torch
+    sk, ctx, K = env[0], env[1], env[2]
+    rng = np.random.default_rng(61)
+    N = 1024
+    tv = rng.integers(0, 1 << 32, N, dtype=np.uint64).astype(np.uint32)
+    n = 11
+    ct = sk.encrypt_bits(rng.integers(0, 2, n).tolist(), nonce=6_400_000)
+    d_tv = torch.from_numpy(tv.view(np.int32).copy()).cuda()
+    d_in = F.to_device(ct)
+    out = torch.empty_like(d_in)
+    try:
+        for shape in [(1, 8, 1), (2, 1, 1), (4, 1, 1), (1, 4, 0)]:
+            F.fhe_ctx_set_launch_config(ctx, 1, 1 << 31, shape)
+            log(f"programmable bootstrap x {n}, shape {shape}")
+            F.fhe_bootstrap_lut_batch(ctx, d_tv, d_in, out, n)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(F.to_host(out), K.bootstrap_lut(tv, ct, threads=8))
+    finally:
+        F.fhe_ctx_set_launch_config(ctx, 1, 1 << 31, (1, 4, 0))
+    f = [3, 0, 2, 1]
+    tv2 = np.array([(f[j * 4 // N] << 29) + (1 << 28) for j in range(N)], np.uint32)
+    ms = np.array([0, 1, 2, 3, 2, 0])
+    bits = sk.encrypt_bits([0] * len(ms), nonce=6_500_000)  # -mu + noise; shift the phase to m/8 + 1/16
+    bits[:, -1] = (bits[:, -1].astype(np.uint64) + (1 << 29) + (ms.astype(np.uint64) << 29) + (1 << 28)) % (1 << 32)
+    d_in2 = F.to_device(bits)
+    out2 = torch.empty_like(d_in2)
+    F.fhe_bootstrap_lut_batch(ctx, torch.from_numpy(tv2.view(np.int32).copy()).cuda(), d_in2, out2, len(ms))
+    torch.cuda.synchronize()
+    got = F.to_host(out2)
+    np.testing.assert_array_equal(got, K.bootstrap_lut(tv2, bits, threads=8))
+    ph = K.phase(got).astype(np.int64) % (1 << 32)
+    assert list((ph >> 29) & 3) == [f[m] for m in ms]
