@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load of the serving leg as a fraction of the batched throughput")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--goldilocks-steps", type=int, default=1,
+                    help="steps timed once more with the NTT over 2^64 - 2^32 + 1 (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +311,36 @@ def main():
                 "gates_per_launch": round(gates_per_launch, 1)}
     per_shape = {f"{k[0]}x{k[1]}/arith{k[2]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
                  for k, v in sorted(by_shape.items())}
+
+    # the same step with the NTT over the Goldilocks prime 2^64 - 2^32 + 1 (one
+    # wave per gate, four gates per workgroup), against its own algorithmic
+    # count; then the tuned shapes are put back
+    goldilocks = None
+    if args.goldilocks_steps > 0:
+        saved = [F.fhe_ctx_launch_config(ctx, 1 << b) for b in range(16)]
+        F.fhe_ctx_set_launch_config(ctx, 1, 1 << 31, (1, 4, 0))
+        step()
+        torch.cuda.synchronize()
+        F.fhe_ctx_timing(ctx)
+        F.fhe_ctx_set_timing(ctx, True)
+        gs0 = time.perf_counter()
+        for _ in range(args.goldilocks_steps):
+            step()
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - gs0) * 1e3 / args.goldilocks_steps
+        F.fhe_ctx_set_timing(ctx, False)
+        grec = [r for r in F.fhe_ctx_timing_launches(ctx) if r["shape"] == (1, 4, 0)]
+        g_gates = sum(r["gates"] for r in grec)
+        g_br = sum(r["blind_rotate_ms"] for r in grec)
+        g_ach = LANE_OPS_PER_GATE[0] * g_gates / (g_br / 1e3) / 1e12
+        goldilocks = {"gates_per_s": round(gates_per_step / (g_ms / 1e3), 1), "ms_per_step": round(g_ms, 1),
+                      "kernel": "k_blind_rotate<4, 0>", "achieved": round(g_ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                      "unit": "TOP/s", "frac": round(g_ach / VALU_PEAK_TOPS, 4)}
+        for b, shp in enumerate(saved):
+            F.fhe_ctx_set_launch_config(ctx, 1 << b, 1 << b, shp)
+        if not np.array_equal(sk.decrypt_uint(F.to_host(dR), width), np.asarray(expect).reshape(-1).astype(np.uint64)):
+            raise SystemExit("bench: Goldilocks-path results differ from plaintext arithmetic")
+        log(f"Goldilocks NTT: {goldilocks}")
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
@@ -459,7 +491,8 @@ def main():
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": workload,
         "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
-        "mul32_karatsuba_latency": mul_kara, "circuit_latency": circuits, "serving": serving,
+        "mul32_karatsuba_latency": mul_kara, "circuit_latency": circuits, "goldilocks_ntt": goldilocks,
+        "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": per_shape},
