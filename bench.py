@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--tune-max-width", type=int, default=4096,
                     help="autotune launch shapes up to this batch width before warmup (0 keeps the defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=300,
+    ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs in the serving leg (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load of the serving leg as a fraction of the batched throughput")
