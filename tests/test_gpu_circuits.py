@@ -107,7 +107,8 @@ def test_matvec_bit_exact(env, rows, cols, width):
 
 def test_add16_full_size(env):
     """1024 pairs of uniform uint16 in one level-scheduled run (the benchmark's
-    launch configuration): every sum decrypts correctly, pair 0 is bit-exact."""
+    launch configuration and balanced schedule): every sum decrypts correctly,
+    pairs 0-7 and the last pair are bit-exact end to end (666 gates)."""
     sk, ctx, K = env
     wl = workloads.AddWorkload()
     a, b = wl.operands()
@@ -116,8 +117,9 @@ def test_add16_full_size(env):
     log("add16 x 1024 pairs")
     got = gpu_binary(ctx, F.fhe_add, ca, cb, wl.count, wl.width)
     np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (a + b) % (1 << wl.width))
-    log("oracle: pair 0 end to end")
-    np.testing.assert_array_equal(got[0], K.add(ca[:1], cb[:1], wl.width)[0])
+    pick = list(range(8)) + [wl.count - 1]
+    log("oracle: pairs 0-7 and 1023 end to end")
+    np.testing.assert_array_equal(got[pick], K.add(ca[pick], cb[pick], wl.width))
 
 
 @pytest.mark.parametrize("width,count", [(1, 1), (5, 2), (8, 3)])
@@ -235,7 +237,7 @@ def test_matmul16_4x4_decrypts(env):
 
 def test_mul32_full_size_decrypts(env):
     """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
-    product decrypts correctly."""
+    product decrypts correctly, pair 0 is bit-exact end to end (2,824 gates)."""
     sk, ctx, K = env
     wl = workloads.MulWorkload()
     a, b = wl.operands()
@@ -245,6 +247,8 @@ def test_mul32_full_size_decrypts(env):
     got = gpu_binary(ctx, F.fhe_mul, ca, cb, wl.count, wl.width)
     want = (a.astype(object) * b.astype(object)) % (1 << 32)
     np.testing.assert_array_equal(sk.decrypt_uint(got, 32).astype(object), want)
+    log("oracle: mul32 pair 0 end to end (2,824 gates)")
+    np.testing.assert_array_equal(got[0], K.mul(ca[:1], cb[:1], wl.width)[0])
 
 
 def test_mul8_in_wide_batch_bit_exact(env):
