@@ -284,6 +284,23 @@ def main():
     graph_ms_per_step = (time.perf_counter() - g0) * 1e3 / args.steps
     log(f"graph replay: {graph_ms_per_step:.1f} ms/step")
 
+    # one step with the inputs copied in from pinned host memory and the
+    # results copied out (the PCIe-inclusive rate; not `value`)
+    hA = dA.cpu().pin_memory()
+    hB = dB.cpu().pin_memory()
+    hR = torch.empty(dR.shape, dtype=dR.dtype).pin_memory()
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    dA.copy_(hA, non_blocking=True)
+    dB.copy_(hB, non_blocking=True)
+    step()
+    hR.copy_(dR, non_blocking=True)
+    torch.cuda.synchronize()
+    e2e_ms = (time.perf_counter() - e0) * 1e3
+    end_to_end = {"gates_per_s": round(gates_per_step / (e2e_ms / 1e3), 1), "ms_per_step": round(e2e_ms, 1),
+                  "bytes_in": int(hA.numel() + hB.numel()) * 4, "bytes_out": int(hR.numel()) * 4}
+    log(f"with host transfers: {end_to_end}")
+
     got = sk.decrypt_uint(F.to_host(dR), width)
     if not np.array_equal(got, np.asarray(expect).reshape(-1).astype(np.uint64)):
         raise SystemExit("bench: decrypted results differ from plaintext arithmetic")
@@ -492,6 +509,7 @@ def main():
         "config": workload,
         "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
         "mul32_karatsuba_latency": mul_kara, "circuit_latency": circuits, "goldilocks_ntt": goldilocks,
+        "with_host_transfers": end_to_end,
         "serving": serving,
         "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
