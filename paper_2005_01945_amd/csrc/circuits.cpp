@@ -364,9 +364,11 @@ static double level_cost(uint64_t gates, uint64_t round) {
 // can run at any level between its ASAP level and its latest level (ALAP)
 // as long as its inputs come from earlier levels and its consumers run
 // later.  Levels (ascending) narrower than one round take the most urgent
-// such gates until they hold one round; the result is kept only if the cost
-// model above says it is faster.  The depth and every gate's inputs and
-// outputs are unchanged, so the words computed are too.
+// such gates until they hold one round; then levels whose last round is
+// partly filled pass that overflow on to later levels with room (below).
+// Of ASAP, filled and filled + trimmed the cost model's cheapest is kept.
+// The depth and every gate's inputs and outputs are unchanged, so the words
+// computed are too.
 static std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_t>& asap, uint32_t depth,
                                             size_t count, uint64_t round) {
     const size_t ng = c.gates.size();
@@ -400,12 +402,50 @@ static std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<
             lev[k] = L;
         }
     }
-    double before = 0, after = 0;
-    for (uint32_t L = 1; L <= depth; ++L) {
-        before += level_cost(width0[L] * count, round);
-        after += level_cost(width[L] * count, round);
+    const std::vector<uint32_t> filled(lev);
+    const std::vector<uint64_t> width1(width);
+    // Trim: a level wider than a round whose last round is partly empty hands
+    // that overflow (gates with slack, those with the most first) to the
+    // earliest later level that has room below its own round boundary and
+    // still precedes the gate's consumers.
+    std::vector<std::vector<uint32_t>> at(depth + 2);
+    for (size_t k = 0; k < ng; ++k) at[lev[k]].push_back((uint32_t)k);
+    auto room = [&](uint32_t L) -> uint64_t {
+        const uint64_t g = width[L] * count;
+        const uint64_t cap = 2 * g > round ? (g + round - 1) / round * round : round;
+        return cap - g;
+    };
+    for (uint32_t L = 1; L < depth; ++L) {
+        const uint64_t g = width[L] * count;
+        if (g <= round || g % round == 0) continue;
+        uint64_t need = (g % round + count - 1) / count;
+        std::vector<uint32_t> cand;
+        for (uint32_t k : at[L])
+            if (alap[k] > L) cand.push_back(k);
+        std::stable_sort(cand.begin(), cand.end(), [&](uint32_t a, uint32_t b) { return alap[a] > alap[b]; });
+        for (uint32_t k : cand) {
+            if (need == 0) break;
+            uint32_t lim = alap[k];
+            for (uint32_t q : cons[k]) lim = std::min(lim, lev[q] - 1);
+            for (uint32_t L2 = L + 1; L2 <= lim; ++L2) {
+                if (room(L2) < count) continue;
+                width[L]--;
+                width[L2]++;
+                lev[k] = L2;
+                at[L2].push_back(k);
+                need--;
+                break;
+            }
+        }
     }
-    return after < before ? lev : asap;
+    double c_asap = 0, c_fill = 0, c_trim = 0;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        c_asap += level_cost(width0[L] * count, round);
+        c_fill += level_cost(width1[L] * count, round);
+        c_trim += level_cost(width[L] * count, round);
+    }
+    if (c_trim < c_fill && c_trim < c_asap) return lev;
+    return c_fill < c_asap ? filled : asap;
 }
 
 // A scheduled, device-resident plan for (kind, width, rows, cols, count).// A scheduled, device-resident plan for (kind, width, rows, cols, count).
