@@ -6,8 +6,11 @@
  * under encryption to reset the noise; Fig. 2: a gate runs its linear
  * combination, bootstrapping with the BS key, then key switching with the KS
  * key), and builds the paper's integer circuits from those gates (Sec. III
- * and V-B: ripple-carry addition, shift-and-add multiplication, vector and
- * matrix products with tree accumulation).
+ * and V-B: ripple-carry and number-wise addition, shift-and-add, tree and
+ * Karatsuba multiplication, vector and matrix products with tree
+ * accumulation, Cannon's matrix product).  It also offers three-input gates
+ * (majority and parity, a full adder per level) and programmable
+ * bootstrapping with a caller's test vector.
  *
  * Conventions
  *  - Every function returns int: FHE_OK (0) or a negative FHE_E* code.  No
@@ -341,13 +344,21 @@ int fhe_circuit_schedule(int kind, uint32_t width, uint32_t rows, uint32_t cols,
 /* ---------------------------------------------------------------------- */
 typedef struct fhe_server fhe_server;
 
-typedef enum { FHE_JOB_GATE = 0, FHE_JOB_ADD = 1, FHE_JOB_MUL = 2, FHE_JOB_MATVEC = 3, FHE_JOB_MUL_TREE = 4 } fhe_job_kind;
+typedef enum {
+    FHE_JOB_GATE = 0, FHE_JOB_ADD = 1, FHE_JOB_MUL = 2, FHE_JOB_MATVEC = 3, FHE_JOB_MUL_TREE = 4,
+    FHE_JOB_ADD_FA = 5, FHE_JOB_ADD_NUMBERWISE = 6, FHE_JOB_KARATSUBA = 7, FHE_JOB_MATMUL = 8
+} fhe_job_kind;
 
 /* One job.  Buffers are DEVICE memory owned by the caller; inputs must be
  * written (their stream synchronized) before submission and stay valid, and
  * `out` is written when the job reaches FHE_JOB_DONE.
  *   GATE:   in0, in1 [1][n+1], op = gate code, out [1][n+1]
- *   ADD/MUL/MUL_TREE: in0, in1, out [width][n+1] (one integer, LSB first)
+ *   ADD/MUL/MUL_TREE/ADD_FA/ADD_NUMBERWISE: in0, in1, out [width][n+1] (one
+ *           integer, LSB first; the circuits of fhe_add, fhe_mul, fhe_mul_tree,
+ *           fhe_add_fa, fhe_add_numberwise)
+ *   KARATSUBA: in0, in1 [width][n+1], out [2 width][n+1] (fhe_mul_karatsuba)
+ *   MATMUL: rows = n; in0 = A, in1 = B, out = C, each [n][n][width][n+1]
+ *           (fhe_matmul)
  *   MATVEC: in0 = M [rows][cols][width][n+1], in1 = x [cols][width][n+1],
  *           out = y [rows][width][n+1]                                        */
 typedef struct {

@@ -406,7 +406,8 @@ def fhe_ctx_timing(ctx):
 # ---------------------------------------------------------------------------
 # Serving
 # ---------------------------------------------------------------------------
-FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC, FHE_JOB_MUL_TREE = range(5)
+(FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC, FHE_JOB_MUL_TREE, FHE_JOB_ADD_FA,
+ FHE_JOB_ADD_NUMBERWISE, FHE_JOB_KARATSUBA, FHE_JOB_MATMUL) = range(9)
 FHE_JOB_QUEUED, FHE_JOB_RUNNING, FHE_JOB_DONE, FHE_JOB_CANCELLED, FHE_JOB_FAILED = range(5)
 
 

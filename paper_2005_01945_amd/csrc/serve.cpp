@@ -1,5 +1,5 @@
-// Serving runtime: continuous batching of gate / add / mul / matvec jobs on one
-// context.
+// Serving runtime: continuous batching of gate and circuit jobs (every circuit
+// of the circuit entry points) on one context.
 //
 // A worker thread owns the context while the server lives.  Each tick it
 //  1. admits queued jobs, in arrival order, whose samples (inputs, every gate
@@ -41,6 +41,8 @@ struct ServeShape {
     uint32_t na = 0, nb = 0, nout = 0, slots = 0;
     std::vector<uint8_t> op;                        // per gate
     std::vector<uint32_t> in0, in1, out;            // pool slots per gate
+    std::vector<uint32_t> in2;                      // third input (kNoWire: none)
+    bool three = false;                             // any three-input gate
     std::vector<std::vector<uint32_t>> levels;      // gate indices per level
 };
 
@@ -52,14 +54,22 @@ ServeShape make_shape(int kind, uint32_t op, uint32_t w, uint32_t rows, uint32_t
         S.op = {(uint8_t)op};
         S.in0 = {0};
         S.in1 = {1};
+        S.in2 = {kNoWire};
         S.out = {2};
         S.levels = {{0}};
         return S;
     }
-    const int ck = kind == FHE_JOB_ADD        ? kAdd
-                   : kind == FHE_JOB_MUL      ? kMul
-                   : kind == FHE_JOB_MUL_TREE ? kMulTree
-                                              : kMatvec;
+    int ck = kMatvec;
+    switch (kind) {
+    case FHE_JOB_ADD: ck = kAdd; break;
+    case FHE_JOB_MUL: ck = kMul; break;
+    case FHE_JOB_MUL_TREE: ck = kMulTree; break;
+    case FHE_JOB_ADD_FA: ck = kAddFa; break;
+    case FHE_JOB_ADD_NUMBERWISE: ck = kAddNumberwise; break;
+    case FHE_JOB_KARATSUBA: ck = kKaratsuba; break;
+    case FHE_JOB_MATMUL: ck = kMatmul; break;
+    default: break;
+    }
     const Circuit c = build_circuit(ck, w, rows, cols);
     uint32_t depth = 0;
     const std::vector<uint32_t> glev = asap_levels(c, &depth);
@@ -79,6 +89,8 @@ ServeShape make_shape(int kind, uint32_t op, uint32_t w, uint32_t rows, uint32_t
         S.op.push_back(g.op);
         S.in0.push_back(slot[g.in0]);
         S.in1.push_back(slot[g.in1]);
+        S.in2.push_back(g.in2 != kNoWire ? slot[g.in2] : kNoWire);
+        S.three |= g.in2 != kNoWire;
         S.out.push_back(slot[g.out]);
         S.levels[glev[k] - 1].push_back((uint32_t)k);
     }
@@ -151,6 +163,8 @@ struct fhe_server {
     hipStream_t stream = nullptr;
     uint4* d_desc = nullptr;
     uint4* h_desc = nullptr;  // pinned staging
+    uint32_t* d_desc3 = nullptr;  // third inputs
+    uint32_t* h_desc3 = nullptr;
     size_t desc_cap = 0;
     std::unique_ptr<SlotAllocator> slots;
 
@@ -173,7 +187,7 @@ namespace {
 const ServeShape* shape_for(fhe_server* S, const fhe_job& j) {
     const uint32_t op = j.kind == FHE_JOB_GATE ? j.op : 0;
     const uint32_t w = j.kind == FHE_JOB_GATE ? 1 : j.width;
-    const uint32_t rows = j.kind == FHE_JOB_MATVEC ? j.rows : 0;
+    const uint32_t rows = j.kind == FHE_JOB_MATVEC || j.kind == FHE_JOB_MATMUL ? j.rows : 0;
     const uint32_t cols = j.kind == FHE_JOB_MATVEC ? j.cols : 0;
     auto key = std::make_tuple((int)j.kind, op, w, rows, cols);
     auto it = S->shapes.find(key);
@@ -187,11 +201,17 @@ int ensure_desc(fhe_server* S, size_t n) {
     cap = std::max<size_t>(cap, 4096);
     if (S->d_desc) (void)hipFree(S->d_desc);
     if (S->h_desc) (void)hipHostFree(S->h_desc);
+    if (S->d_desc3) (void)hipFree(S->d_desc3);
+    if (S->h_desc3) (void)hipHostFree(S->h_desc3);
     S->d_desc = nullptr;
     S->h_desc = nullptr;
+    S->d_desc3 = nullptr;
+    S->h_desc3 = nullptr;
     S->desc_cap = 0;
     hipError_t e = hipMalloc((void**)&S->d_desc, cap * sizeof(uint4));
     if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_desc, cap * sizeof(uint4), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->d_desc3, cap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_desc3, cap * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "serving descriptors");
     S->desc_cap = cap;
     return FHE_OK;
@@ -205,6 +225,7 @@ void worker_loop(fhe_server* S) {
     std::vector<Job*> tick;
     for (;;) {
         size_t ngates = 0;
+        bool three = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // retire cancelled running jobs
@@ -261,19 +282,26 @@ void worker_loop(fhe_server* S) {
                 continue;
             }
             size_t k = 0;
+            three = false;
             for (Job* j : tick) {
                 const ServeShape& sh = *j->shape;
-                for (uint32_t g : sh.levels[j->level])
+                three |= sh.three;
+                for (uint32_t g : sh.levels[j->level]) {
+                    S->h_desc3[k] = sh.in2[g] != kNoWire ? pool_wire(j->base + sh.in2[g]) : 0u;
                     S->h_desc[k++] = make_uint4(sh.op[g], pool_wire(j->base + sh.in0[g]),
                                                 pool_wire(j->base + sh.in1[g]), pool_wire(j->base + sh.out[g]));
+                }
             }
         }
         // one launch pair for the whole frontier
         hipError_t e = hipMemcpyAsync(S->d_desc, S->h_desc, ngates * sizeof(uint4), hipMemcpyHostToDevice, S->stream);
+        if (e == hipSuccess && three)
+            e = hipMemcpyAsync(S->d_desc3, S->h_desc3, ngates * sizeof(uint32_t), hipMemcpyHostToDevice, S->stream);
         int rc = e == hipSuccess ? FHE_OK : hip_fail(e, "serving descriptor upload");
         if (rc == FHE_OK) {
             dev::GateIO io{};
             io.desc = S->d_desc;
+            io.desc3 = three ? S->d_desc3 : nullptr;
             io.region[3] = S->pool;
             rc = run_gate_batch(S->ctx, io, ngates, S->stream);
         }
@@ -341,12 +369,16 @@ extern "C" int fhe_serve_create(fhe_ctx* ctx, size_t hbm_budget_bytes, fhe_serve
 extern "C" int fhe_serve_submit(fhe_server* S, const fhe_job* job, uint64_t* ticket) {
     if (!S || !job || !ticket) return set_error(FHE_EINVAL, "fhe_serve_submit: null argument");
     const fhe_job& j = *job;
-    if (j.kind > FHE_JOB_MUL_TREE) return set_error(FHE_EINVAL, "fhe_serve_submit: job kind %u", j.kind);
+    if (j.kind > FHE_JOB_MATMUL) return set_error(FHE_EINVAL, "fhe_serve_submit: job kind %u", j.kind);
     if (j.kind == FHE_JOB_GATE && j.op > FHE_ORYN) return set_error(FHE_EINVAL, "fhe_serve_submit: gate code %u", j.op);
     if (j.kind != FHE_JOB_GATE && (j.width < 1 || j.width > 64))
         return set_error(FHE_EINVAL, "fhe_serve_submit: width %u", j.width);
     if (j.kind == FHE_JOB_MATVEC && (j.rows == 0 || j.cols == 0 || j.rows > 4096 || j.cols > 4096))
         return set_error(FHE_EINVAL, "fhe_serve_submit: matrix %ux%u", j.rows, j.cols);
+    if (j.kind == FHE_JOB_MATMUL && (j.rows == 0 || j.rows > 64))
+        return set_error(FHE_EINVAL, "fhe_serve_submit: matrix dimension %u", j.rows);
+    if (j.kind == FHE_JOB_KARATSUBA && j.width < 2)
+        return set_error(FHE_EINVAL, "fhe_serve_submit: Karatsuba width %u", j.width);
     if (!j.in0 || !j.in1 || !j.out) return set_error(FHE_EINVAL, "fhe_serve_submit: null buffer");
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->fatal) return set_error(S->fatal, "fhe_serve_submit: server stopped after a device error");
@@ -436,6 +468,8 @@ extern "C" void fhe_serve_destroy(fhe_server* S) {
         if (S->pool) (void)hipFree(S->pool);
         if (S->d_desc) (void)hipFree(S->d_desc);
         if (S->h_desc) (void)hipHostFree(S->h_desc);
+        if (S->d_desc3) (void)hipFree(S->d_desc3);
+        if (S->h_desc3) (void)hipHostFree(S->h_desc3);
         if (S->stream) (void)hipStreamDestroy(S->stream);
     }
     for (auto& kv : S->jobs) delete kv.second;

@@ -25,7 +25,8 @@ def env():
 
 def make_jobs(sk):
     """A small mix: two gates, an add16, an add32, a mul8 (shift-and-add and
-    tree accumulation) and a 2x3 4-bit matvec."""
+    tree accumulation), 8-bit additions with full-adder gates and number-wise,
+    a 6-bit Karatsuba product, a 2x3 4-bit matvec and a 2x2 3-bit matmul."""
     import torch
     jobs = []
     nonce = 3_000_000
@@ -35,17 +36,30 @@ def make_jobs(sk):
         jobs.append(dict(kind=F.FHE_JOB_GATE, op=op, a=a, b=b, shape=(1, F.WORDS),
                          want=[[1 - (k & 1), (k & 1) ^ 1][k]], width=1))
     for kind, w, x, y in [(F.FHE_JOB_ADD, 16, 51234, 40000), (F.FHE_JOB_ADD, 32, 4000000000, 500000000),
-                          (F.FHE_JOB_MUL, 8, 201, 77), (F.FHE_JOB_MUL_TREE, 8, 201, 77)]:
+                          (F.FHE_JOB_MUL, 8, 201, 77), (F.FHE_JOB_MUL_TREE, 8, 201, 77),
+                          (F.FHE_JOB_ADD_FA, 8, 200, 99), (F.FHE_JOB_ADD_NUMBERWISE, 8, 255, 1),
+                          (F.FHE_JOB_KARATSUBA, 6, 61, 45)]:
         a = sk.encrypt_uint([x], w, nonce=nonce); nonce += w
         b = sk.encrypt_uint([y], w, nonce=nonce); nonce += w
-        res = (x + y) % (1 << w) if kind == F.FHE_JOB_ADD else (x * y) % (1 << w)
-        jobs.append(dict(kind=kind, op=0, a=a, b=b, shape=(w, F.WORDS), want=[res], width=w))
+        if kind in (F.FHE_JOB_ADD, F.FHE_JOB_ADD_FA, F.FHE_JOB_ADD_NUMBERWISE):
+            res, ow = (x + y) % (1 << w), w
+        elif kind == F.FHE_JOB_KARATSUBA:
+            res, ow = x * y, 2 * w
+        else:
+            res, ow = (x * y) % (1 << w), w
+        jobs.append(dict(kind=kind, op=0, a=a, b=b, shape=(ow, F.WORDS), want=[res], width=w, out_width=ow))
     M = np.array([[3, 9, 15], [7, 1, 12]], np.uint64)
     v = np.array([5, 11, 2], np.uint64)
     a = sk.encrypt_uint(M.reshape(-1), 4, nonce=nonce); nonce += 24
     b = sk.encrypt_uint(v, 4, nonce=nonce); nonce += 12
     jobs.append(dict(kind=F.FHE_JOB_MATVEC, op=0, a=a, b=b, shape=(2, 4, F.WORDS), want=list((M @ v) % 16),
                      width=4, rows=2, cols=3))
+    A = np.array([[5, 7], [2, 6]], np.uint64)
+    B = np.array([[3, 1], [4, 7]], np.uint64)
+    a = sk.encrypt_uint(A.reshape(-1), 3, nonce=nonce); nonce += 12
+    b = sk.encrypt_uint(B.reshape(-1), 3, nonce=nonce); nonce += 12
+    jobs.append(dict(kind=F.FHE_JOB_MATMUL, op=0, a=a, b=b, shape=(4, 3, F.WORDS),
+                     want=list(((A @ B) % 8).reshape(-1)), width=3, rows=2))
     for j in jobs:
         j["da"], j["db"] = F.to_device(j["a"]), F.to_device(j["b"])
     torch.cuda.synchronize()
@@ -80,7 +94,8 @@ def test_alone_equals_mix_and_decrypts(env):
         for j, o, a in zip(jobs, outs, alone):
             got = F.to_host(o)
             np.testing.assert_array_equal(got, a)
-            dec = sk.decrypt_uint(got, j["width"]) if j["kind"] != F.FHE_JOB_GATE else sk.decrypt_bits(got)
+            dec = sk.decrypt_uint(got, j.get("out_width", j["width"])) if j["kind"] != F.FHE_JOB_GATE \
+                else sk.decrypt_bits(got)
             assert list(dec) == list(j["want"]), (j["kind"], list(dec), j["want"])
         stats = F.fhe_serve_stats(srv)
         assert stats["jobs_done"] == 2 * len(jobs) and stats["pool_bytes_in_use"] == 0
@@ -109,7 +124,7 @@ def test_small_budget_queues_and_refuses(env):
         ref = F.to_host(outs[0])
         for o in outs[1:]:
             np.testing.assert_array_equal(F.to_host(o), ref)
-        matvec = jobs[-1]
+        matvec = next(j for j in jobs if j["kind"] == F.FHE_JOB_MATVEC)  # larger than the budget
         with pytest.raises(F.FheError) as e:
             submit(srv, matvec, torch.zeros(matvec["shape"], dtype=torch.int32, device="cuda"))
         assert e.value.code == F.FHE_EBUSY
