@@ -267,6 +267,27 @@ int fhe_matvec(fhe_ctx* ctx, const uint32_t* M, const uint32_t* x, uint32_t* y, 
 int fhe_matmul(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* C, uint32_t n,
                uint32_t width, void* stream);
 
+/* Caller-defined circuits: any DAG of gates, run by the same level scheduler
+ * as the circuits above (ASAP levels balanced to whole launch rounds, one
+ * launch pair per level over all instances, captured HIP graphs).
+ * Wires: 0 .. n_inputs-1 are a instance's inputs; gate k writes wire
+ * n_inputs + k and may read only wires below that.  in2 is read only by
+ * FHE_MAJ and FHE_XOR3.  outputs lists distinct gate-output wires.
+ * fhe_circuit_run: in = device uint32[count][n_inputs][n+1], out =
+ * [count][n_outputs][n+1], asynchronous on `stream`.  Destroy a circuit
+ * before its context; fhe_circuit_destroy waits for the device.
+ * EINVAL: a gate reading an undefined wire, an unknown gate code, an output
+ * that is an input or repeated, null pointers. */
+typedef struct {
+    uint8_t op;
+    uint32_t in0, in1, in2;
+} fhe_gate_node;
+typedef struct fhe_circuit fhe_circuit;
+int fhe_circuit_create(fhe_ctx* ctx, const fhe_gate_node* gates, uint32_t n_gates, uint32_t n_inputs,
+                       const uint32_t* outputs, uint32_t n_outputs, fhe_circuit** out);
+int fhe_circuit_run(fhe_circuit* c, const uint32_t* in, uint32_t* out, size_t count, void* stream);
+void fhe_circuit_destroy(fhe_circuit* c);
+
 /* Circuit calls replay their level schedule as a captured HIP graph (one
  * per circuit shape and set of buffers, captured on first use; kernel
  * launches only).  enable = 0 launches every level directly instead.

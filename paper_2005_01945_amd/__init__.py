@@ -73,6 +73,9 @@ _SIGS = {
     "fhe_bootstrap_gate3_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_bootstrap_lut_batch": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
+    "fhe_circuit_create": (C.c_int, [_vp, _vp, C.c_uint32, C.c_uint32, _vp, C.c_uint32, C.POINTER(_vp)]),
+    "fhe_circuit_run": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_circuit_destroy": (None, [_vp]),
     "fhe_mul_karatsuba": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matvec": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_schedule": (C.c_int, [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32,
@@ -409,6 +412,37 @@ def fhe_ctx_timing(ctx):
 (FHE_JOB_GATE, FHE_JOB_ADD, FHE_JOB_MUL, FHE_JOB_MATVEC, FHE_JOB_MUL_TREE, FHE_JOB_ADD_FA,
  FHE_JOB_ADD_NUMBERWISE, FHE_JOB_KARATSUBA, FHE_JOB_MATMUL) = range(9)
 FHE_JOB_QUEUED, FHE_JOB_RUNNING, FHE_JOB_DONE, FHE_JOB_CANCELLED, FHE_JOB_FAILED = range(5)
+
+
+class fhe_gate_node(C.Structure):
+    _fields_ = [("op", C.c_uint8), ("in0", C.c_uint32), ("in1", C.c_uint32), ("in2", C.c_uint32)]
+
+
+class Circuit:
+    """fhe_circuit: a caller-defined gate DAG run by the level scheduler.
+    gates: list of (op, in0, in1) or (op, in0, in1, in2) over wires (inputs
+    0..n_inputs-1, gate k writes wire n_inputs + k); outputs: gate wires."""
+
+    def __init__(self, ctx, gates, n_inputs, outputs):
+        arr = (fhe_gate_node * len(gates))()
+        for k, g in enumerate(gates):
+            arr[k] = fhe_gate_node(g[0], g[1], g[2], g[3] if len(g) > 3 else 0xFFFFFFFF)
+        outs = (C.c_uint32 * len(outputs))(*outputs)
+        h = _vp()
+        _check(lib().fhe_circuit_create(ctx.h, C.cast(arr, _vp), len(gates), n_inputs, C.cast(outs, _vp),
+                                        len(outputs), C.byref(h)), "fhe_circuit_create")
+        self.h, self.ctx, self.n_inputs, self.n_outputs = h.value, ctx, n_inputs, len(outputs)
+
+    def run(self, inp, out, count, stream=None):
+        _check(lib().fhe_circuit_run(self.h, _dev(inp), _dev(out), count, _stream(stream)), "fhe_circuit_run")
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fhe_circuit_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class fhe_job(C.Structure):

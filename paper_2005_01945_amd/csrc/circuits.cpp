@@ -470,8 +470,12 @@ struct CapturedRun {
 struct CircuitCache {
     std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, size_t>, Plan> plans;
     std::map<std::tuple<const Plan*, const void*, const void*, const void*>, CapturedRun> graphs;
+    std::map<uint32_t, Circuit> custom;  // caller-defined circuits by id (plans: kind kCustom, rows = id)
+    uint32_t next_custom = 1;
     uint64_t clock = 0;
 };
+
+constexpr int kCustom = 1000;
 
 constexpr size_t kMaxGraphs = 64;
 
@@ -482,7 +486,7 @@ constexpr uint32_t kRegionA = 0, kRegionB = 1, kRegionR = 2, kRegionPool = 3;
 uint32_t wire_id(uint32_t region, uint64_t index) { return (region << 30) | (uint32_t)index; }
 
 int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols, size_t count, Plan* P) {
-    const Circuit c = build_circuit(kind, w, rows, cols);
+    const Circuit c = kind == kCustom ? ctx->circuits->custom.at(rows) : build_circuit(kind, w, rows, cols);
     uint32_t depth = 0;
     const std::vector<uint32_t> asap = asap_levels(c, &depth);
     const std::vector<uint32_t> glev = balance_levels(c, asap, depth, count, 8 * (uint64_t)ctx->cu_count);
@@ -654,6 +658,29 @@ int run_circuit(fhe_ctx* ctx, int kind, const uint32_t* A, const uint32_t* B, ui
 
 }  // namespace
 
+// Frees the plans and graphs of caller-defined circuit `id` and forgets it.
+static void drop_custom(fhe_ctx* ctx, uint32_t id) {
+    CircuitCache& C = *ctx->circuits;
+    for (auto it = C.plans.begin(); it != C.plans.end();) {
+        if (std::get<0>(it->first) == kCustom && std::get<2>(it->first) == id) {
+            const Plan* P = &it->second;
+            for (auto g = C.graphs.begin(); g != C.graphs.end();) {
+                if (std::get<0>(g->first) == P) {
+                    drop_graph(g->second);
+                    g = C.graphs.erase(g);
+                } else {
+                    ++g;
+                }
+            }
+            free_plan(it->second);
+            it = C.plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    C.custom.erase(id);
+}
+
 void destroy_circuit_cache(fhe_ctx* ctx) {
     if (!ctx->circuits) return;
     for (auto& kv : ctx->circuits->graphs) drop_graph(kv.second);
@@ -742,4 +769,66 @@ extern "C" int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32
     if (levels) *levels = depth;
     if (widest_level) *widest_level = *std::max_element(per.begin(), per.end());
     return FHE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Caller-defined circuits.
+// ---------------------------------------------------------------------------
+struct fhe_circuit {
+    fhe_ctx* ctx = nullptr;
+    uint32_t id = 0, n_inputs = 0, n_outputs = 0;
+};
+
+extern "C" int fhe_circuit_create(fhe_ctx* ctx, const fhe_gate_node* gates, uint32_t n_gates, uint32_t n_inputs,
+                                  const uint32_t* outputs, uint32_t n_outputs, fhe_circuit** out) {
+    if (!ctx || !out || (n_gates && !gates) || !outputs)
+        return set_error(FHE_EINVAL, "fhe_circuit_create: null argument");
+    *out = nullptr;
+    if (n_inputs == 0 || n_outputs == 0 || n_gates == 0 || n_inputs >= (1u << 24) || n_gates >= (1u << 24))
+        return set_error(FHE_EINVAL, "fhe_circuit_create: %u inputs, %u gates, %u outputs", n_inputs, n_gates,
+                         n_outputs);
+    Circuit c;
+    c.na = n_inputs;
+    c.nb = 0;
+    for (uint32_t k = 0; k < n_gates; ++k) {
+        const fhe_gate_node& g = gates[k];
+        const uint32_t lim = n_inputs + k;  // wires defined before gate k
+        const bool three = g.op == FHE_MAJ || g.op == FHE_XOR3;
+        if (g.op > FHE_XOR3 || g.in0 >= lim || g.in1 >= lim || (three && g.in2 >= lim))
+            return set_error(FHE_EINVAL, "fhe_circuit_create: gate %u (op %u) reads a wire not defined before it", k,
+                             g.op);
+        c.gates.push_back({g.op, g.in0, g.in1, lim, three ? g.in2 : kNoWire});
+    }
+    std::vector<bool> seen(n_inputs + n_gates, false);
+    for (uint32_t j = 0; j < n_outputs; ++j) {
+        if (outputs[j] < n_inputs || outputs[j] >= n_inputs + n_gates || seen[outputs[j]])
+            return set_error(FHE_EINVAL, "fhe_circuit_create: output %u must be a distinct gate output", j);
+        seen[outputs[j]] = true;
+        c.outputs.push_back(outputs[j]);
+    }
+    fhe_circuit* h = new (std::nothrow) fhe_circuit();
+    if (!h) return set_error(FHE_ENOMEM, "fhe_circuit_create: out of host memory");
+    if (!ctx->circuits) ctx->circuits = new CircuitCache();
+    h->ctx = ctx;
+    h->id = ctx->circuits->next_custom++;
+    h->n_inputs = n_inputs;
+    h->n_outputs = n_outputs;
+    ctx->circuits->custom[h->id] = std::move(c);
+    *out = h;
+    return FHE_OK;
+}
+
+extern "C" int fhe_circuit_run(fhe_circuit* c, const uint32_t* in, uint32_t* out, size_t count, void* stream) {
+    if (!c) return set_error(FHE_EINVAL, "fhe_circuit_run: null circuit");
+    return run_circuit(c->ctx, kCustom, in, in, out, count, 1, c->id, 0, (hipStream_t)stream, "fhe_circuit_run");
+}
+
+extern "C" void fhe_circuit_destroy(fhe_circuit* c) {
+    if (!c) return;
+    if (c->ctx && c->ctx->circuits) {
+        DeviceGuard guard(c->ctx->device);
+        (void)hipDeviceSynchronize();  // runs may still be in flight on callers' streams
+        drop_custom(c->ctx, c->id);
+    }
+    delete c;
 }

@@ -298,3 +298,57 @@ def test_matvec64_full_size_decrypts(env):
     torch.cuda.synchronize()
     got = F.to_host(dy)
     np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (M @ x) % (1 << wl.width))
+
+
+def test_custom_circuit_bit_exact(env):
+    """A caller-defined random DAG (two- and three-input gates, outputs taken
+    from several depths) over 5 instances, against the oracle evaluating the
+    same gates one by one; invalid circuits are refused."""
+    import torch
+    sk, ctx, K = env
+    rng = np.random.default_rng(150)
+    n_in, n_gates, count = 6, 60, 5
+    gates = []
+    for k in range(n_gates):
+        lim = n_in + k
+        op = int(rng.integers(0, 12))
+        a, b, c = (int(rng.integers(max(0, lim - 12), lim)) for _ in range(3))
+        gates.append((op, a, b, c) if op >= 10 else (op, a, b))
+    outputs = [n_in + k for k in (5, 23, 40, 59, 58)]
+    circ = F.Circuit(ctx, gates, n_in, outputs)
+    bits = rng.integers(0, 2, (count, n_in))
+    cin = sk.encrypt_bits(bits.reshape(-1).tolist(), nonce=2_500_000).reshape(count, n_in, -1)
+    d_in = F.to_device(cin)
+    d_out = torch.empty((count, len(outputs), F.WORDS), dtype=torch.int32, device="cuda")
+    log("custom circuit: 60 gates x 5 instances")
+    circ.run(d_in, d_out, count)
+    torch.cuda.synchronize()
+    got = F.to_host(d_out)
+    # the oracle: wire by wire, all instances of one gate in one call
+    wires = [cin[:, i, :] for i in range(n_in)]
+    for g in gates:
+        if g[0] >= 10:
+            wires.append(K.bootstrap3([g[0]] * count, wires[g[1]], wires[g[2]], wires[g[3]], threads=8))
+        else:
+            wires.append(K.bootstrap([g[0]] * count, wires[g[1]], wires[g[2]], threads=8))
+    want = np.stack([wires[o] for o in outputs], axis=1)
+    np.testing.assert_array_equal(got, want)
+    # plaintext check of the outputs through decryption
+    vals = [bits[:, i] for i in range(n_in)]
+    tt = [lambda x, y: x & y, lambda x, y: 1 - (x & y), lambda x, y: x | y, lambda x, y: 1 - (x | y),
+          lambda x, y: x ^ y, lambda x, y: 1 - (x ^ y), lambda x, y: (1 - x) & y, lambda x, y: x & (1 - y),
+          lambda x, y: (1 - x) | y, lambda x, y: x | (1 - y)]
+    for g in gates:
+        if g[0] == F.MAJ:
+            vals.append((vals[g[1]] + vals[g[2]] + vals[g[3]] >= 2).astype(int))
+        elif g[0] == F.XOR3:
+            vals.append((vals[g[1]] + vals[g[2]] + vals[g[3]]) & 1)
+        else:
+            vals.append(tt[g[0]](vals[g[1]], vals[g[2]]))
+    dec = sk.decrypt_bits(got.reshape(-1, F.WORDS)).reshape(count, len(outputs))
+    np.testing.assert_array_equal(dec, np.stack([vals[o] for o in outputs], axis=1))
+    circ.close()
+    for bad_gates, bad_out in [([(0, 0, 7)], [6]), ([(12, 0, 1)], [6]), ([(0, 0, 1)], [0]), ([(0, 0, 1)], [6, 6]),
+                               ([(10, 0, 1, 6)], [6])]:
+        with pytest.raises(F.FheError):
+            F.Circuit(ctx, bad_gates, n_in, bad_out)
