@@ -259,6 +259,11 @@ constexpr int first_same_tw(int kind, int L, int k) {
 template <int I, int KIND, int IN>
 MQ_FN void ntt32(int32_t (&x)[32]) {
     using P = PlanOf<KIND, IN>;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // A wave in a transform (VALU only) takes issue priority over its SIMD's
+    // other wave, which meanwhile runs its LDS and memory phases.
+    __builtin_amdgcn_s_setprio(1);
+#endif
     static_for<0, 5>([&](auto L_) {
         constexpr int L = decltype(L_)::value;
         stage_fence();
@@ -317,6 +322,9 @@ MQ_FN void ntt32(int32_t (&x)[32]) {
         });
     });
     stage_fence();
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_s_setprio(0);
+#endif
 }
 
 }  // namespace mq
