@@ -1150,81 +1150,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
         if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
 }
 
-// Key switching of wide batches: the 24 KSK rows of one input coefficient
-// (48 KB) are staged in LDS once per workgroup of eight gates (one wave
-// each) and every wave subtracts its eight rows from there, instead of each
-// gate gathering its rows from L2.  Double-buffered: the rows of coefficient
-// i + 1 are loaded while those of i are used.  Faster than k_key_switch only
-// when a level has many rounds of gates (measured: 25 vs 38 ms at 31,744
-// gates, equal at 8,192, slower below).
-constexpr int kKsRowsPerCoef = 3 * (int)kKsT;                          // 24
-constexpr int kKsVecsPerCoef = kKsRowsPerCoef * (int)kKskRowWords / 4;  // uint4s, 3072
-constexpr int kKsLdsThreads = 512;
-constexpr uint32_t kKsLdsMinGates = 16384;
-
-__global__ __launch_bounds__(kKsLdsThreads) void k_key_switch_lds(DeviceKeys K, GateIO io,
-                                                                  const uint32_t* __restrict__ big,
-                                                                  uint32_t count) {
-    __shared__ uint4 rows[2][kKsVecsPerCoef];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint32_t g = blockIdx.x * (kKsLdsThreads / 64) + wave;
-    const bool active = g < count;  // uniform per wave; every wave takes part in the staging
-    const uint32_t* src = big + (size_t)(active ? g : blockIdx.x * (kKsLdsThreads / 64)) * (N + 1);
-    uint32_t acc[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) acc[e] = (8 * lane + e == NLWE) ? src[N] : 0u;
-    const uint4* ksk = reinterpret_cast<const uint4*>(K.ksk) + tid;
-    constexpr int kPer = kKsVecsPerCoef / kKsLdsThreads;  // 6
-    static_assert(kKsVecsPerCoef % kKsLdsThreads == 0, "staging split");
-    uint4 st[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) rows[0][tid + kKsLdsThreads * k] = ksk[kKsLdsThreads * k];
-    __syncthreads();
-#pragma unroll 1
-    for (int i0 = 0; i0 < N; i0 += 64) {
-        const uint32_t digits = (src[i0 + lane] + (1u << 15)) >> 16;
-#pragma unroll 1
-        for (int l = 0; l < 64; ++l) {
-            const int i = i0 + l, buf = i & 1;
-            const bool more = i + 1 < N;
-            if (more) {
-#pragma unroll
-                for (int k = 0; k < kPer; ++k) st[k] = ksk[(size_t)(i + 1) * kKsVecsPerCoef + kKsLdsThreads * k];
-            }
-            if (active) {
-                const uint32_t dd = __builtin_amdgcn_readlane(digits, l);
-#pragma unroll
-                for (int j = 0; j < (int)kKsT; ++j) {
-                    const uint32_t d = (dd >> (14 - 2 * j)) & 3u;
-                    if (d) {
-                        const uint4* row = &rows[buf][(3 * j + d - 1) * (kKskRowWords / 4)];
-                        const uint4 v0 = row[2 * lane], v1 = row[2 * lane + 1];
-                        acc[0] -= v0.x; acc[1] -= v0.y; acc[2] -= v0.z; acc[3] -= v0.w;
-                        acc[4] -= v1.x; acc[5] -= v1.y; acc[6] -= v1.z; acc[7] -= v1.w;
-                    }
-                }
-            }
-            if (more) {
-#pragma unroll
-                for (int k = 0; k < kPer; ++k) rows[buf ^ 1][tid + kKsLdsThreads * k] = st[k];
-            }
-            __syncthreads();
-        }
-    }
-    if (!active) return;
-    uint32_t* o = gate_output(io, g);
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-        if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
-}
-
-// Key switching of narrow batches, for latency: eight waves per gate, wave w
-// summing the rows of coefficients 128w .. 128w + 127; the eight partial
-// sums meet in LDS and wave 0 writes the result.  A gate's key switch then
-// takes about an eighth of the one-wave time (the rows of one wave are
-// fetched one coefficient after another).
+// Key switching with eight waves per gate: wave w sums the rows of
+// coefficients 128w .. 128w + 127, the eight partial sums meet in LDS and
+// wave 0 writes the result.  Eight times the waves in flight of the one-wave
+// kernel hides the latency of the row gathers; measured faster at every
+// batch width except 2,561 .. 4,096 gates (16,384 gates: 8.5 vs 17.3 ms for
+// one wave per gate, and 12.4 ms when the rows of a coefficient are staged
+// in LDS once per workgroup of eight gates).
 constexpr int kKsSplitWaves = 8;
-constexpr uint32_t kKsSplitMaxGates = 1024;
+constexpr uint32_t kKsOneWaveMin = 2561, kKsOneWaveMax = 4096;
 
 __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceKeys K, GateIO io,
                                                                         const uint32_t* __restrict__ big,
@@ -1417,18 +1351,12 @@ hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* 
 hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
                              uint32_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    if (count >= kKsLdsMinGates) {
-        const uint32_t per = kKsLdsThreads / 64;
-        hipLaunchKernelGGL(k_key_switch_lds, dim3((count + per - 1) / per), dim3(kKsLdsThreads), 0, s, K, io, big,
-                           count);
+    if (count >= kKsOneWaveMin && count <= kKsOneWaveMax) {
+        const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(k_key_switch, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
         return hipGetLastError();
     }
-    if (count <= kKsSplitMaxGates) {
-        hipLaunchKernelGGL(k_key_switch_split, dim3(count), dim3(64 * kKsSplitWaves), 0, s, K, io, big, count);
-        return hipGetLastError();
-    }
-    const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_key_switch, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
+    hipLaunchKernelGGL(k_key_switch_split, dim3(count), dim3(64 * kKsSplitWaves), 0, s, K, io, big, count);
     return hipGetLastError();
 }
 

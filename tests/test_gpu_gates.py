@@ -177,13 +177,13 @@ def test_noise_variance_over_16k_bootstraps(env):
     np.testing.assert_array_equal(sk.decrypt_bits(got), want)
 
 
-def test_wide_ragged_batch_sampled_bit_exact(env):
-    """A 16,385-gate batch (key switching staged through LDS for wide
-    batches, with a last workgroup of one gate): sampled gates, the first
-    and last among them, bit-exact against the oracle, every gate decrypting
-    to its truth table."""
+@pytest.mark.parametrize("n", [16385, 3001, 1537])
+def test_wide_ragged_batch_sampled_bit_exact(env, n):
+    """Wide batches on both key-switching kernels (eight waves per gate at
+    16,385 and 1,537 gates, one wave per gate at 3,001 with a last workgroup
+    of one gate): sampled gates, the first and last among them, bit-exact
+    against the oracle, every gate decrypting to its truth table."""
     sk, ctx, K = env
-    n = 16385
     ops = workloads.gate_ops(500, n)
     A = workloads.bits(501, n).astype(int)
     B = workloads.bits(502, n).astype(int)
@@ -194,7 +194,7 @@ def test_wide_ragged_batch_sampled_bit_exact(env):
     table = np.array([A & B, 1 - (A & B), A | B, 1 - (A | B), A ^ B, 1 - (A ^ B),
                       (1 - A) & B, A & (1 - B), (1 - A) | B, A | (1 - B)])
     np.testing.assert_array_equal(sk.decrypt_bits(got), table[ops.astype(int), np.arange(n)])
-    pick = np.array([0, 1, 8191, 16383, 16384])
+    pick = np.array([0, 1, n // 2, n - 2, n - 1])
     log("oracle: 5 sampled gates")
     np.testing.assert_array_equal(got[pick], K.bootstrap(ops[pick], c0[pick], c1[pick], threads=5))
 
