@@ -77,6 +77,7 @@ def lib():
             "or_blind_rotate": (None, [KP, u32p, u32p]),
             "or_blind_rotate_tv": (None, [KP, u32p, u32p, u32p]),
             "or_sample_extract": (None, [PP, u32p, u32p]),
+            "or_sample_extract_at": (None, [PP, u32p, C.c_int32, u32p]),
             "or_key_switch": (None, [KP, u32p, u32p]),
             "or_bootstrap_gate": (None, [KP, C.c_int, u32p, u32p, u32p]),
             "or_bootstrap_gates": (None, [KP, u8p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
@@ -213,6 +214,13 @@ class Keys:
         a = _c(acc, np.uint32).reshape(-1)
         out = np.empty(self.P.N + 1, np.uint32)
         lib().or_sample_extract(C.byref(self.P), _u32p(a), _u32p(out))
+        return out
+
+    def sample_extract_at(self, acc, m: int) -> np.ndarray:
+        """LWE sample (under the TLWE key's coefficients) of coefficient m of the TLWE sample acc."""
+        a = _c(acc, np.uint32).reshape(-1)
+        out = np.empty(self.P.N + 1, np.uint32)
+        lib().or_sample_extract_at(C.byref(self.P), _u32p(a), m, _u32p(out))
         return out
 
     def key_switch(self, lwe_big) -> np.ndarray:

@@ -366,6 +366,18 @@ void or_sample_extract(const or_params* P, const uint32_t* acc, uint32_t* lwe_bi
     lwe_big[N] = acc[N];
 }
 
+/* Sample extraction of coefficient m of a TLWE sample (A, B): the LWE sample
+ * under the coefficients of S whose phase is coefficient m of B - A S.  From
+ * (A S)_m = sum_{j <= m} A_(m-j) S_j - sum_{j > m} A_(N+m-j) S_j:
+ *   a'_j = A_(m-j) for j <= m,  a'_j = -A_(N+m-j) for j > m,  b' = B_m. */
+void or_sample_extract_at(const or_params* P, const uint32_t* acc, int32_t m, uint32_t* lwe_big) {
+    const int32_t N = P->N;
+    const uint32_t* A = acc;
+    const uint32_t* B = acc + N;
+    for (int32_t j = 0; j < N; j++) lwe_big[j] = j <= m ? A[m - j] : (uint32_t)0 - A[N + m - j];
+    lwe_big[N] = B[m];
+}
+
 /* Key switching N -> n with unsigned base-2^basebit digits of a'_i rounded to
  * t*basebit bits:  out = (0, b') - sum_{i, jj} KSK[i][jj][d_{i,jj}]. */
 void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out) {

@@ -106,6 +106,9 @@ void or_blind_rotate_tv(const or_keys* K, const uint32_t* lwe_in, const uint32_t
 void or_bootstrap_lut(const or_keys* K, const uint32_t* tv, const uint32_t* in, uint32_t* out, size_t count,
                       int threads);
 void or_sample_extract(const or_params* P, const uint32_t* acc, uint32_t* lwe_big);
+/* Extraction of coefficient m (0 <= m < N): the phase of the result is
+ * coefficient m of the TLWE phase B - A S (m = 0: or_sample_extract). */
+void or_sample_extract_at(const or_params* P, const uint32_t* acc, int32_t m, uint32_t* lwe_big);
 void or_key_switch(const or_keys* K, const uint32_t* lwe_big, uint32_t* out);
 
 /* One bootstrapped gate; threads = 0 means all online cores. */
