@@ -78,6 +78,8 @@ def lib():
             "or_blind_rotate_tv": (None, [KP, u32p, u32p, u32p]),
             "or_sample_extract": (None, [PP, u32p, u32p]),
             "or_sample_extract_at": (None, [PP, u32p, C.c_int32, u32p]),
+            "or_compound_combine": (C.c_int, [PP, C.c_int, u32p, u32p]),
+            "or_bootstrap_compounds": (C.c_int, [KP, u8p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_key_switch": (None, [KP, u32p, u32p]),
             "or_bootstrap_gate": (None, [KP, C.c_int, u32p, u32p, u32p]),
             "or_bootstrap_gates": (None, [KP, u8p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
@@ -88,6 +90,7 @@ def lib():
             "or_circuit_add_numberwise": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_circuit_matmul": (None, [KP, u32p, u32p, u32p, C.c_int32, C.c_int32, C.c_int]),
             "or_circuit_add_fa": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
+            "or_circuit_add_compound": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int32, C.c_int]),
             "or_bootstrap_lut": (None, [KP, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_bootstrap_gates3": (None, [KP, u8p, u32p, u32p, u32p, u32p, C.c_size_t, C.c_int]),
             "or_circuit_eval_plain": (C.c_long, [C.c_int, C.c_int32, C.c_int32, C.c_int32, u8p, u8p]),
@@ -240,6 +243,20 @@ class Keys:
         lib().or_bootstrap_gates(self.ref(), _u8p(o), _u32p(a), _u32p(b), _u32p(out), o.size, threads)
         return out
 
+    def bootstrap_compound(self, ops, in0, in1, threads: int = 0) -> np.ndarray:
+        """Compound gates (Sec. V-A-3): ops [count][2] symmetric codes; out
+        [count][2][n+1] = (ops[g][0](in0[g], in1[g]), ops[g][1](in0[g], in1[g]))
+        from one blind rotation per g."""
+        o = _c(ops, np.uint8).reshape(-1, 2)
+        a = _c(in0, np.uint32).reshape(-1, self.width)
+        b = _c(in1, np.uint32).reshape(-1, self.width)
+        assert a.shape[0] == o.shape[0] and b.shape[0] == o.shape[0]
+        out = np.empty((o.shape[0], 2, self.width), np.uint32)
+        rc = lib().or_bootstrap_compounds(self.ref(), _u8p(o), _u32p(a), _u32p(b), _u32p(out), o.shape[0], threads)
+        if rc:
+            raise ValueError("compound gates take symmetric codes only (AND, NAND, OR, NOR, XOR, XNOR)")
+        return out
+
     # --- circuits ---
     def add(self, A, B, width: int, threads: int = 0) -> np.ndarray:
         a = _c(A, np.uint32).reshape(-1, width, self.width)
@@ -277,6 +294,14 @@ class Keys:
         b = _c(B, np.uint32).reshape(-1, width, self.width)
         out = np.empty_like(a)
         lib().or_circuit_add_fa(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
+        return out
+
+    def add_compound(self, A, B, width: int, threads: int = 0) -> np.ndarray:
+        """(A + B) mod 2^width, eqs. (1)-(2) with compound (XOR, AND) gates (Sec. V-A-3)."""
+        a = _c(A, np.uint32).reshape(-1, width, self.width)
+        b = _c(B, np.uint32).reshape(-1, width, self.width)
+        out = np.empty_like(a)
+        lib().or_circuit_add_compound(self.ref(), _u32p(a), _u32p(b), _u32p(out), a.shape[0], width, threads)
         return out
 
     def bootstrap3(self, ops, in0, in1, in2, threads: int = 0) -> np.ndarray:
@@ -331,6 +356,17 @@ def negacyclic_mul(P, Q) -> np.ndarray:
     return out
 
 
+def compound_combine(op: int, acc, params: Params = None) -> np.ndarray:
+    """The compound gate's N-dimensional sample of symmetric code op from the
+    rotated accumulator acc [2][N] (before key switching)."""
+    P = params if params is not None else default_params()
+    a = _c(acc, np.uint32).reshape(-1)
+    out = np.empty(P.N + 1, np.uint32)
+    if lib().or_compound_combine(C.byref(P), op, _u32p(a), _u32p(out)):
+        raise ValueError("not a symmetric gate code")
+    return out
+
+
 def rotate(P, a: int) -> np.ndarray:
     p = _c(P, np.uint32)
     out = np.empty_like(p)
@@ -370,7 +406,7 @@ def cmux(bk_i, abar: int, acc, params: Params = None) -> np.ndarray:
 
 def circuit_gate_count(kind: str, width: int, rows: int = 0, cols: int = 0) -> int:
     k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
-         "matmul": 6, "add_fa": 7}[kind]
+         "matmul": 6, "add_fa": 7, "add_compound": 8}[kind]
     return lib().or_circuit_gate_count(k, width, rows, cols)
 
 
@@ -378,7 +414,7 @@ def circuit_eval_plain(kind: str, width: int, operand_bits, rows: int = 0, cols:
     """A circuit's gates evaluated on plaintext bits (uint8 0/1, operands LSB
     first, A then B or M then x; matmul: rows = n); returns the result bits."""
     k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
-         "matmul": 6, "add_fa": 7}[kind]
+         "matmul": 6, "add_fa": 7, "add_compound": 8}[kind]
     bits = _c(operand_bits, np.uint8)
     nout = {"matvec": rows * width, "matmul": rows * rows * width, "karatsuba": 2 * width}.get(kind, width)
     out = np.empty(nout, np.uint8)

@@ -496,6 +496,133 @@ void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Compound gates (Sec. V-A-3): two gates on the same two inputs, here from  */
+/* ONE blind rotation.                                                        */
+/* ------------------------------------------------------------------------ */
+/* Value (+1 true, -1 false) of a symmetric two-input gate with k of its two
+ * inputs true; 0 for a code that is not symmetric. */
+static int sym_truth(int op, int k) {
+    switch (op) {
+    case OR_AND: return k == 2 ? 1 : -1;
+    case OR_NAND: return k == 2 ? -1 : 1;
+    case OR_OR: return k >= 1 ? 1 : -1;
+    case OR_NOR: return k >= 1 ? -1 : 1;
+    case OR_XOR: return k == 1 ? 1 : -1;
+    case OR_XNOR: return k == 1 ? -1 : 1;
+    default: return 0;
+    }
+}
+
+/* The compound gate rotates the constant test vector 1/16 by the phase of
+ * c1 + c2, which is -1/4, 0 or +1/4 for k = 0, 1, 2 true inputs (encoding
+ * +-1/8).  Coefficient m of the rotated accumulator encrypts U(phibar + m),
+ * U = +1/16 on [0, N) and -1/16 on [N, 2N) (negacyclic); the extractions at
+ * m = 3N/4 and m = N/4 (E1, E2) take the values
+ *     k = 0 (phibar = -N/2):  E1 = +1/16, E2 = -1/16
+ *     k = 1 (phibar = 0):     E1 = +1/16, E2 = +1/16
+ *     k = 2 (phibar = +N/2):  E1 = -1/16, E2 = +1/16
+ * and switch sign exactly half-way between those phases, like the two-input
+ * gates.  A symmetric gate with values g0, g1, g2 (units of 1/8) is then the
+ * sample (g1 - g2) E1 + (g1 - g0) E2 + (0, (g0 + g2) / 16): at each k it
+ * evaluates to g_k / 8.  This writes that N-dimensional sample (before key
+ * switching) into big; returns -1 for a code that is not symmetric. */
+int or_compound_combine(const or_params* P, int op, const uint32_t* acc, uint32_t* big) {
+    const int32_t N = P->N;
+    const int g0 = sym_truth(op, 0), g1 = sym_truth(op, 1), g2 = sym_truth(op, 2);
+    if (!g0) return -1;
+    uint32_t* e1 = (uint32_t*)malloc((size_t)(N + 1) * sizeof(uint32_t));
+    uint32_t* e2 = (uint32_t*)malloc((size_t)(N + 1) * sizeof(uint32_t));
+    or_sample_extract_at(P, acc, 3 * N / 4, e1);
+    or_sample_extract_at(P, acc, N / 4, e2);
+    const uint32_t x = (uint32_t)(g1 - g2), y = (uint32_t)(g1 - g0);
+    for (int32_t j = 0; j <= N; j++) big[j] = x * e1[j] + y * e2[j];
+    big[N] += (uint32_t)(g0 + g2) * (1u << 28);
+    free(e1);
+    free(e2);
+    return 0;
+}
+
+/* out0 = op0(c1, c2), out1 = op1(c1, c2) for symmetric codes op0, op1 (AND,
+ * NAND, OR, NOR, XOR, XNOR): one blind rotation of the constant test vector
+ * 1/16 by c1 + c2, two combinations of its extracted coefficients, two key
+ * switchings.  Returns -1 (and writes nothing) for other codes. */
+int or_bootstrap_compound(const or_keys* K, int op0, int op1, const uint32_t* c1, const uint32_t* c2,
+                          uint32_t* out0, uint32_t* out1) {
+    const or_params* P = &K->P;
+    if (!sym_truth(op0, 0) || !sym_truth(op1, 0)) return -1;
+    uint32_t* comb = (uint32_t*)malloc((size_t)(P->n + 1) * sizeof(uint32_t));
+    uint32_t* tv = (uint32_t*)malloc((size_t)P->N * sizeof(uint32_t));
+    uint32_t* acc = (uint32_t*)malloc(2u * (size_t)P->N * sizeof(uint32_t));
+    uint32_t* big = (uint32_t*)malloc((size_t)(P->N + 1) * sizeof(uint32_t));
+    for (int32_t i = 0; i <= P->n; i++) comb[i] = c1[i] + c2[i];
+    for (int32_t j = 0; j < P->N; j++) tv[j] = 1u << 28;
+    or_blind_rotate_tv(K, comb, tv, acc);
+    or_compound_combine(P, op0, acc, big);
+    or_key_switch(K, big, out0);
+    or_compound_combine(P, op1, acc, big);
+    or_key_switch(K, big, out1);
+    free(comb);
+    free(tv);
+    free(acc);
+    free(big);
+    return 0;
+}
+
+typedef struct {
+    const or_keys* K;
+    const uint8_t* ops;
+    const uint32_t* in0;
+    const uint32_t* in1;
+    uint32_t* out;
+    size_t count, next;
+    int bad;
+    pthread_mutex_t lock;
+} compound_job;
+
+static void* compound_worker(void* arg) {
+    compound_job* J = (compound_job*)arg;
+    const size_t W = (size_t)J->K->P.n + 1;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        size_t g = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (g >= J->count) break;
+        if (or_bootstrap_compound(J->K, J->ops[2 * g], J->ops[2 * g + 1], J->in0 + g * W, J->in1 + g * W,
+                                  J->out + 2 * g * W, J->out + (2 * g + 1) * W)) {
+            pthread_mutex_lock(&J->lock);
+            J->bad = 1;
+            pthread_mutex_unlock(&J->lock);
+        }
+    }
+    return NULL;
+}
+
+static int resolve_threads(int threads);
+
+int or_bootstrap_compounds(const or_keys* K, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                           uint32_t* out, size_t count, int threads) {
+    if (count == 0) return 0;
+    compound_job J;
+    J.K = K;
+    J.ops = ops;
+    J.in0 = in0;
+    J.in1 = in1;
+    J.out = out;
+    J.count = count;
+    J.next = 0;
+    J.bad = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    int T = resolve_threads(threads);
+    if ((size_t)T > count) T = (int)count;
+    pthread_t* tid = (pthread_t*)malloc((size_t)T * sizeof(pthread_t));
+    for (int i = 0; i < T; i++) pthread_create(&tid[i], NULL, compound_worker, &J);
+    for (int i = 0; i < T; i++) pthread_join(tid[i], NULL);
+    free(tid);
+    pthread_mutex_destroy(&J.lock);
+    return J.bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Running independent gates on several threads.                             */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -505,6 +632,8 @@ typedef struct {
     const uint32_t* const* in1;
     const uint32_t* const* in2; /* NULL: two-input gates only */
     uint32_t* const* out;
+    const int* ops2;            /* NULL, or per gate: >= 0 for a compound node */
+    uint32_t* const* out2;      /* its second output */
     size_t count;
     size_t next;
     pthread_mutex_t lock;
@@ -517,7 +646,9 @@ static void* gate_worker(void* arg) {
         size_t g = J->next++;
         pthread_mutex_unlock(&J->lock);
         if (g >= J->count) break;
-        if (J->in2)
+        if (J->ops2 && J->ops2[g] >= 0)
+            or_bootstrap_compound(J->K, J->ops[g], J->ops2[g], J->in0[g], J->in1[g], J->out[g], J->out2[g]);
+        else if (J->in2)
             or_bootstrap_gate3(J->K, J->ops[g], J->in0[g], J->in1[g], J->in2[g], J->out[g]);
         else
             or_bootstrap_gate(J->K, J->ops[g], J->in0[g], J->in1[g], J->out[g]);
@@ -532,10 +663,11 @@ static int resolve_threads(int threads) {
     return c > 16 ? 16 : c > 0 ? (int)c : 1;
 }
 
-/* Runs gate g on (in0[g], in1[g]) -> out[g] for g < count, pointer form. */
-static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* const* in0,
-                      const uint32_t* const* in1, const uint32_t* const* in2, uint32_t* const* out,
-                      size_t count, int threads) {
+/* Runs gate g on (in0[g], in1[g]) -> out[g] for g < count, pointer form;
+ * compound nodes (ops2[g] >= 0) also write out2[g]. */
+static void run_gates_c(const or_keys* K, const uint8_t* ops, const uint32_t* const* in0,
+                        const uint32_t* const* in1, const uint32_t* const* in2, uint32_t* const* out,
+                        const int* ops2, uint32_t* const* out2, size_t count, int threads) {
     if (count == 0) return;
     gate_job J;
     J.K = K;
@@ -544,6 +676,8 @@ static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* cons
     J.in1 = in1;
     J.in2 = in2;
     J.out = out;
+    J.ops2 = ops2;
+    J.out2 = out2;
     J.count = count;
     J.next = 0;
     pthread_mutex_init(&J.lock, NULL);
@@ -554,6 +688,12 @@ static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* cons
     for (int i = 0; i < T; i++) pthread_join(tid[i], NULL);
     free(tid);
     pthread_mutex_destroy(&J.lock);
+}
+
+static void run_gates(const or_keys* K, const uint8_t* ops, const uint32_t* const* in0,
+                      const uint32_t* const* in1, const uint32_t* const* in2, uint32_t* const* out,
+                      size_t count, int threads) {
+    run_gates_c(K, ops, in0, in1, in2, out, NULL, NULL, count, threads);
 }
 
 void or_bootstrap_gates(const or_keys* K, const uint8_t* ops, const uint32_t* in0,
@@ -596,7 +736,9 @@ void or_bootstrap_gates3(const or_keys* K, const uint8_t* ops, const uint32_t* i
 /* ------------------------------------------------------------------------ */
 /* Circuits as gate lists over wires (each wire holds one LWE sample).        */
 /* ------------------------------------------------------------------------ */
-typedef struct { int op, in0, in1, in2, out; } or_gate_t; /* in2 < 0: two inputs */
+/* in2 < 0: two inputs.  op2 >= 0: a compound node writing op(in0, in1) to
+ * out and op2(in0, in1) to out2 from one rotation (or_bootstrap_compound). */
+typedef struct { int op, in0, in1, in2, out, op2, out2; } or_gate_t;
 typedef struct { or_gate_t* g; long ng, cap; long nwires; } or_prog;
 
 static long new_wire(or_prog* pr) { return pr->nwires++; }
@@ -613,10 +755,44 @@ static long emit3(or_prog* pr, int op, long a, long b, long c) {
     G->in1 = (int)b;
     G->in2 = (int)c;
     G->out = (int)o;
+    G->op2 = -1;
+    G->out2 = -1;
     return o;
 }
 
 static long emit(or_prog* pr, int op, long a, long b) { return emit3(pr, op, a, b, -1); }
+
+/* Compound node: *o0 = op0(a, b), *o1 = op1(a, b). */
+static void emit_compound(or_prog* pr, int op0, int op1, long a, long b, long* o0, long* o1) {
+    *o0 = emit(pr, op0, a, b);
+    or_gate_t* G = &pr->g[pr->ng - 1];
+    G->op2 = op1;
+    G->out2 = (int)new_wire(pr);
+    *o1 = G->out2;
+}
+
+/* Ripple-carry adder of eqs. (1)-(2) with compound gates (Sec. V-A-3): the
+ * XOR and the AND of the same two bits come from one compound node.
+ *   bit 0:     (r, c) = (a ^ b, a & b)
+ *   bit i:     (t, g) = (a ^ b, a & b), (r, h) = (t ^ c, t & c), c = g | h
+ *   bit w-1:   t = a ^ b, r = t ^ c                                         */
+static void build_add_compound(or_prog* pr, const long* a, const long* b, int w, long* r) {
+    if (w <= 0) return;
+    if (w == 1) { r[0] = emit(pr, OR_XOR, a[0], b[0]); return; }
+    long c;
+    emit_compound(pr, OR_XOR, OR_AND, a[0], b[0], &r[0], &c);
+    for (int i = 1; i < w; i++) {
+        if (i == w - 1) {
+            long t = emit(pr, OR_XOR, a[i], b[i]);
+            r[i] = emit(pr, OR_XOR, t, c);
+            break;
+        }
+        long t, g, h;
+        emit_compound(pr, OR_XOR, OR_AND, a[i], b[i], &t, &g);
+        emit_compound(pr, OR_XOR, OR_AND, t, c, &r[i], &h);
+        c = emit(pr, OR_OR, g, h);
+    }
+}
 
 /* Ripple-carry adder of eqs. (1)-(2), sum modulo 2^w (carry out dropped):
  *   bit 0:     r = a ^ b,            c = a & b
@@ -923,6 +1099,7 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
         long l = level[G->in0] > level[G->in1] ? level[G->in0] : level[G->in1];
         if (G->in2 >= 0 && level[G->in2] > l) l = level[G->in2];
         level[G->out] = 1 + l;
+        if (G->out2 >= 0) level[G->out2] = 1 + l;
         if (level[G->out] > maxlev) maxlev = level[G->out];
     }
     uint8_t* ops = (uint8_t*)malloc((size_t)pr->ng + 1);
@@ -930,6 +1107,8 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
     const uint32_t** b = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*b));
     const uint32_t** c = (const uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*c));
     uint32_t** o = (uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*o));
+    int* ops2 = (int*)malloc(((size_t)pr->ng + 1) * sizeof(int));
+    uint32_t** o2 = (uint32_t**)malloc(((size_t)pr->ng + 1) * sizeof(*o2));
     for (long L = 1; L <= maxlev; L++) {
         size_t cnt = 0;
         int three = 0;
@@ -942,10 +1121,14 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
             c[cnt] = G->in2 >= 0 ? wires + (size_t)G->in2 * W : a[cnt]; /* (unread by two-input gates) */
             three |= G->in2 >= 0;
             o[cnt] = wires + (size_t)G->out * W;
+            ops2[cnt] = G->op2;
+            o2[cnt] = G->out2 >= 0 ? wires + (size_t)G->out2 * W : NULL;
             cnt++;
         }
-        run_gates(K, ops, a, b, three ? c : NULL, o, cnt, threads);
+        run_gates_c(K, ops, a, b, three ? c : NULL, o, ops2, o2, cnt, threads);
     }
+    free(ops2);
+    free(o2);
     free(level);
     free(ops);
     free(a);
@@ -955,7 +1138,7 @@ static void run_prog(const or_keys* K, const or_prog* pr, uint32_t* wires, int t
 }
 
 enum { KIND_ADD = 0, KIND_MUL = 1, KIND_MATVEC = 2, KIND_MUL_TREE = 3, KIND_KARATSUBA = 4, KIND_ADD_NUMBERWISE = 5,
-       KIND_MATMUL = 6, KIND_ADD_FA = 7 };
+       KIND_MATMUL = 6, KIND_ADD_FA = 7, KIND_ADD_COMPOUND = 8 };
 
 static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const uint32_t* B,
                            uint32_t* R, size_t count, int32_t width, int threads) {
@@ -976,6 +1159,7 @@ static void circuit_binary(const or_keys* K, int kind, const uint32_t* A, const 
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, outw + c * ow);
         else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, outw + c * ow);
+        else if (kind == KIND_ADD_COMPOUND) build_add_compound(&pr, ia, ib, width, outw + c * ow);
         else build_mul(&pr, ia, ib, width, outw + c * ow);
     }
     uint32_t* wires = (uint32_t*)malloc((size_t)pr.nwires * W * sizeof(uint32_t));
@@ -1014,6 +1198,11 @@ void or_circuit_karatsuba(const or_keys* K, const uint32_t* A, const uint32_t* B
 void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                                size_t count, int32_t width, int threads) {
     circuit_binary(K, KIND_ADD_NUMBERWISE, A, B, R, count, width, threads);
+}
+
+void or_circuit_add_compound(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                             size_t count, int32_t width, int threads) {
+    circuit_binary(K, KIND_ADD_COMPOUND, A, B, R, count, width, threads);
 }
 
 void or_circuit_add_fa(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
@@ -1161,6 +1350,7 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, res);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, res);
         else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, res);
+        else if (kind == KIND_ADD_COMPOUND) build_add_compound(&pr, ia, ib, width, res);
         else build_mul(&pr, ia, ib, width, res);
         free(ia);
         free(ib);
@@ -1174,6 +1364,7 @@ long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, 
             v[G->out] = (uint8_t)(G->op == OR_MAJ ? n1 >= 2 : n1 & 1);
         } else {
             v[G->out] = (uint8_t)plain_gate(G->op, v[G->in0], v[G->in1]);
+            if (G->out2 >= 0) v[G->out2] = (uint8_t)plain_gate(G->op2, v[G->in0], v[G->in1]);
         }
     }
     for (long q = 0; q < nout; q++) out[q] = v[res[q]];
@@ -1207,6 +1398,7 @@ long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols) 
         else if (kind == KIND_KARATSUBA) build_karatsuba(&pr, ia, ib, width, r);
         else if (kind == KIND_ADD_NUMBERWISE) build_add_numberwise(&pr, ia, ib, width, r);
         else if (kind == KIND_ADD_FA) build_add_fa(&pr, ia, ib, width, r);
+        else if (kind == KIND_ADD_COMPOUND) build_add_compound(&pr, ia, ib, width, r);
         else build_mul(&pr, ia, ib, width, r);
         free(ia);
         free(ib);

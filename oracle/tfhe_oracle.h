@@ -127,6 +127,17 @@ void or_bootstrap_gate(const or_keys* K, int op, const uint32_t* c1,
 void or_bootstrap_gates(const or_keys* K, const uint8_t* ops, const uint32_t* in0,
                         const uint32_t* in1, uint32_t* out, size_t count, int threads);
 
+/* ---- compound gates: two symmetric gates on the same inputs, one rotation ---- */
+/* The N-dimensional sample of symmetric gate `op` combined from the blind
+ * rotation acc of the constant test vector 1/16 by c1 + c2 (before key
+ * switching); -1 for a code other than AND, NAND, OR, NOR, XOR, XNOR. */
+int or_compound_combine(const or_params* P, int op, const uint32_t* acc, uint32_t* big);
+int or_bootstrap_compound(const or_keys* K, int op0, int op1, const uint32_t* c1, const uint32_t* c2,
+                          uint32_t* out0, uint32_t* out1);
+/* ops [count][2], in0/in1 [count][n+1], out [count][2][n+1]; -1 if a code is invalid. */
+int or_bootstrap_compounds(const or_keys* K, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                           uint32_t* out, size_t count, int threads);
+
 /* ---- circuits on encrypted integers (width ciphertexts, LSB first) ---- */
 void or_circuit_add(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                     size_t count, int32_t width, int threads);
@@ -146,6 +157,9 @@ void or_circuit_add_numberwise(const or_keys* K, const uint32_t* A, const uint32
                                size_t count, int32_t width, int threads);
 void or_circuit_matvec(const or_keys* K, const uint32_t* M, const uint32_t* x, uint32_t* y,
                        int32_t rows, int32_t cols, int32_t width, int threads);
+/* (A + B) mod 2^width, eqs. (1)-(2) with compound (XOR, AND) nodes (Sec. V-A-3). */
+void or_circuit_add_compound(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
+                             size_t count, int32_t width, int threads);
 /* (A + B) mod 2^width by a ripple carry of full-adder gates (XOR3, MAJ). */
 void or_circuit_add_fa(const or_keys* K, const uint32_t* A, const uint32_t* B, uint32_t* R,
                        size_t count, int32_t width, int threads);
@@ -158,7 +172,8 @@ void or_circuit_matmul(const or_keys* K, const uint32_t* A, const uint32_t* B, u
 long or_circuit_eval_plain(int kind, int32_t width, int32_t rows, int32_t cols, const uint8_t* in, uint8_t* out);
 /* Number of bootstrapped gates the circuits above evaluate (no evaluation);
  * kind 0 add, 1 mul, 2 matvec, 3 mul with tree accumulation, 4 Karatsuba,
- * 5 number-wise add, 6 Cannon matmul (rows = n), 7 full-adder add. */
+ * 5 number-wise add, 6 Cannon matmul (rows = n), 7 full-adder add, 8 add with
+ * compound nodes (a compound node counts once). */
 long or_circuit_gate_count(int kind, int32_t width, int32_t rows, int32_t cols);
 
 #ifdef __cplusplus

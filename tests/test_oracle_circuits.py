@@ -21,12 +21,13 @@ def value(b):
 WANT = {"add": lambda a, b, w: (a + b) % (1 << w),
         "add_numberwise": lambda a, b, w: (a + b) % (1 << w),
         "add_fa": lambda a, b, w: (a + b) % (1 << w),
+        "add_compound": lambda a, b, w: (a + b) % (1 << w),
         "mul": lambda a, b, w: (a * b) % (1 << w),
         "mul_tree": lambda a, b, w: (a * b) % (1 << w),
         "karatsuba": lambda a, b, w: a * b}
 
 
-@pytest.mark.parametrize("kind", ["add", "add_numberwise", "add_fa", "mul", "mul_tree", "karatsuba"])
+@pytest.mark.parametrize("kind", ["add", "add_numberwise", "add_fa", "add_compound", "mul", "mul_tree", "karatsuba"])
 def test_exhaustive_narrow(kind):
     for w in range(2 if kind == "karatsuba" else 1, 6):
         for a in range(1 << w):
@@ -48,6 +49,7 @@ def test_random_wide_products(w):
         assert value(oracle.circuit_eval_plain("add", w, ab)) == (a + b) % (1 << w)
         assert value(oracle.circuit_eval_plain("add_numberwise", w, ab)) == (a + b) % (1 << w)
         assert value(oracle.circuit_eval_plain("add_fa", w, ab)) == (a + b) % (1 << w)
+        assert value(oracle.circuit_eval_plain("add_compound", w, ab)) == (a + b) % (1 << w)
     top = (1 << w) - 1  # all ones: every carry chain at its longest
     assert value(oracle.circuit_eval_plain("karatsuba", w, bits(top, w) * 2)) == top * top
     one = bits(1, w)  # 2^w - 1 + 1: a carry through every round of the number-wise adder
@@ -105,3 +107,11 @@ def test_full_adder_gate_count():
     assert oracle.circuit_gate_count("add_fa", 1) == 1
     for w in range(2, 40):
         assert oracle.circuit_gate_count("add_fa", w) == 2 * w - 1
+
+
+def test_compound_adder_gate_count():
+    """Compound (XOR, AND) nodes at bit 0 and twice per middle bit, one OR per
+    middle bit, two XORs at the top bit: 3w - 3 bootstraps for w >= 2."""
+    assert oracle.circuit_gate_count("add_compound", 1) == 1
+    for w in range(2, 40):
+        assert oracle.circuit_gate_count("add_compound", w) == 3 * w - 3
