@@ -1,9 +1,12 @@
 """Benchmark: bootstrapped gates/s on one MI355X, batched vs plain, plus the
 latency of one 32-bit multiplication.
 
-One step = one batched 16-bit ripple-carry addition of 1024 encrypted pairs
-(75,776 bootstrapped gates in 30 levels, each level one launch pair), with
-inputs resident in HBM.  Prints one JSON line.
+One step = one batched 32-bit multiplication of 256 encrypted pairs
+(shift-and-add keeping the low 32 bits: 722,944 bootstrapped gates in 120
+levels, each level one launch pair), with inputs resident in HBM.  The
+batched 16-bit addition of 1024 pairs (75,776 gates) and the 64x64 16-bit
+matrix-vector product (2,952,576 gates) are timed as legs beside it.  Prints
+one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config add16|mul32|matvec]
                   [--plain-reps R] [--mul-samples S] [--no-cpu-baseline]
@@ -19,6 +22,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402  (seeded plaintext inputs only)
 
 # Algorithmic work of one gate bootstrap, in 32-bit integer lane operations,
 # for the radix-2 NTT form of the method: 500 CMux x (6 NTT-1024 of 5,120
@@ -36,6 +41,14 @@ LANE_OPS_PER_GATE = {
 }
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Key switching gathers rows of the key-switching key: per gate 1,024 input
+# coefficients x 8 base-4 digits, three quarters of them non-zero on average,
+# each selecting one 501-word row (2,004 B).  The 50 MB key is far larger
+# than one XCD's 4 MB L2 but rows are shared by the gates of a launch, so the
+# gathers are served mostly from L2: the roof is the aggregate L2 bandwidth,
+# 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
+KS_BYTES_PER_GATE = 1024 * 8 * 3 // 4 * 501 * 4
+L2_PEAK_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blind_rotate_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2005_01945_amd", "csrc", f)
                for f in ("kernels.hip", "goldilocks.h", "modq.h")]
@@ -75,49 +88,82 @@ def host_threads():
     return max(1, n)
 
 
-def cpu_baseline(sk, a, b, width, sample_gates):
-    """The oracle on the host cores, on the first level of the same addition
-    workload (independent XOR/AND gates of fresh inputs)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def level1_sample(sk, config, count):
+    """`count` gates of the first level of a workload: its operand-bit gates
+    (AND of a_i, b_j for the multiplier; XOR / AND of a_i, b_i for the adder),
+    on fresh encryptions of the workload's operands."""
+    if config == "add16":
+        wl = workloads.AddWorkload()
+        pairs = [(op, c, i, i) for c in range(wl.count) for i in range(wl.width) for op in (4, 0)]
+    else:
+        wl = workloads.MulWorkload()
+        pairs = [(0, c, j, i) for c in range(wl.count) for i in range(wl.width) for j in range(wl.width - i)]
+    a, b = wl.operands()
+    pairs = pairs[:count]
+    used = sorted({p[1] for p in pairs})
+    ca = sk.encrypt_uint(a[used], wl.width, nonce=0)
+    cb = sk.encrypt_uint(b[used], wl.width, nonce=1 << 40)
+    row = {c: k for k, c in enumerate(used)}
+    ops = np.array([p[0] for p in pairs], np.uint8)
+    i0 = np.stack([ca[row[p[1]], p[2]] for p in pairs])
+    i1 = np.stack([cb[row[p[1]], p[3]] for p in pairs])
+    return ops, i0, i1
+
+
+def cpu_baseline(sk, config, sample_gates, single_gates, gates_per_step):
+    """The oracle on the host cores (all threads, then one) on level-1 gates of
+    the benchmark's workload; every bootstrap costs the same, so the per-gate
+    rate extrapolates to whole workloads (labelled as extrapolated)."""
     import oracle
     K = oracle.Keys(0)
-    ca = sk.encrypt_uint(a[: sample_gates], width, nonce=0)
-    cb = sk.encrypt_uint(b[: sample_gates], width, nonce=1 << 40)
-    ops, i0, i1 = [], [], []
-    for c in range(sample_gates):
-        for bit in range(width):
-            for op in (4, 0):  # XOR, AND of (a_i, b_i)
-                if len(ops) < sample_gates:
-                    ops.append(op)
-                    i0.append(ca[c, bit])
-                    i1.append(cb[c, bit])
+    sample = "add16" if config == "add16" else "mul32"
+    ops, i0, i1 = level1_sample(sk, sample, sample_gates)
     threads = host_threads()
     t0 = time.perf_counter()
-    K.bootstrap(ops, np.array(i0), np.array(i1), threads=threads)
+    K.bootstrap(ops, i0, i1, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(len(ops) / dt, 3), "unit": "gates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(ops)} gates of level 1 of the add16 workload (XOR/AND of fresh inputs), "
-                      f"{dt:.1f} s on {threads} threads; per-gate work is identical on every level"}
+    rate = len(ops) / dt
+    t0 = time.perf_counter()
+    K.bootstrap(ops[:single_gates], i0[:single_gates], i1[:single_gates], threads=1)
+    dt1 = time.perf_counter() - t0
+    rate1 = single_gates / dt1
+    full = {name: round(g / rate / 3600, 2) for name, g in gates_per_step.items()}
+    return {"value": round(rate, 3), "unit": "gates/s", "cores": threads, "kind": "oracle",
+            "single_core_gates_per_s": round(rate1, 3), "cpu_model": cpu_model(),
+            "sample": f"{len(ops)} gates of level 1 of the {sample} workload on {threads} threads ({dt:.1f} s), "
+                      f"{single_gates} of them on one thread ({dt1:.1f} s); every bootstrap does the same work",
+            "extrapolated_full_config_hours": full}
 
 
 JOB_GATES = None
 
 
 def serving_leg(F, sk, ctx, rate_gates_per_s, n_jobs, budget_bytes, seed=3):
-    """Poisson stream of mixed jobs (single gates, add16, add32, mul32, 8x8
-    8-bit matvec) offered at rate_gates_per_s; every job is checked against
-    plaintext arithmetic after the run."""
+    """Poisson stream of mixed jobs (single gates, add16, add32, mul32 with
+    tree accumulation, 8x8 8-bit matvec) offered at rate_gates_per_s; every
+    job is checked against plaintext arithmetic after the run."""
     import torch
-    import workloads
-    kinds = {"gate": (F.FHE_JOB_GATE, 1, 1), "add16": (F.FHE_JOB_ADD, 16, None), "add32": (F.FHE_JOB_ADD, 32, None),
-             "mul32": (F.FHE_JOB_MUL, 32, None), "matvec8": (F.FHE_JOB_MATVEC, 8, None)}
+    kinds = {"gate": (F.FHE_JOB_GATE, 1), "add16": (F.FHE_JOB_ADD, 16), "add32": (F.FHE_JOB_ADD, 32),
+             "mul32": (F.FHE_JOB_MUL_TREE, 32), "matvec8": (F.FHE_JOB_MATVEC, 8)}
     gates_of = {"gate": 1, "add16": F.fhe_circuit_shape("add", 16)[0], "add32": F.fhe_circuit_shape("add", 32)[0],
-                "mul32": F.fhe_circuit_shape("mul", 32)[0], "matvec8": F.fhe_circuit_shape("matvec", 8, 8, 8)[0]}
+                "mul32": F.fhe_circuit_shape("mul_tree", 32)[0], "matvec8": F.fhe_circuit_shape("matvec", 8, 8, 8)[0]}
     mean_gates = sum(p * gates_of[k] for k, p in zip(workloads.JOB_KINDS, workloads.JOB_MIX))
     jobs = workloads.job_stream(seed, n_jobs, rate_gates_per_s / mean_gates)
     prepared = []
     nonce = 1 << 56
     for j in jobs:
-        kind, w, _ = kinds[j.kind]
+        kind, w = kinds[j.kind]
         if j.kind == "gate":
             a = sk.encrypt_bits(j.a, nonce=nonce); b = sk.encrypt_bits(j.b, nonce=nonce + 1); nonce += 2
             shape, rows, cols = (1, F.WORDS), 0, 0
@@ -150,11 +196,15 @@ def serving_leg(F, sk, ctx, rate_gates_per_s, n_jobs, budget_bytes, seed=3):
         F.fhe_serve_wait(srv, t, 1200)
     t1 = time.perf_counter()
     stats = F.fhe_serve_stats(srv)
-    lat = {}
+    lat, wait, serv = {}, {}, {}
     bad = 0
     for p, t in zip(prepared, tickets):
         st, ms = F.fhe_serve_poll(srv, t)
-        lat.setdefault(p["j"].kind, []).append(ms)
+        q, v = F.fhe_serve_job_times(srv, t)
+        k = p["j"].kind
+        lat.setdefault(k, []).append(ms)
+        wait.setdefault(k, []).append(q)
+        serv.setdefault(k, []).append(v)
         host = F.to_host(p["out"])
         dec = sk.decrypt_bits(host) if p["kind"] == F.FHE_JOB_GATE else sk.decrypt_uint(host, p["w"])
         bad += list(dec) != list(p["want"])
@@ -162,11 +212,144 @@ def serving_leg(F, sk, ctx, rate_gates_per_s, n_jobs, budget_bytes, seed=3):
     if bad:
         raise SystemExit(f"bench: {bad} served jobs decrypted wrongly")
     total_gates = sum(gates_of[p["j"].kind] for p in prepared)
-    return {"jobs": len(prepared), "gates": total_gates, "offered_gates_per_s": round(rate_gates_per_s, 1),
-            "served_gates_per_s": round(total_gates / (t1 - t0), 1), "wall_s": round(t1 - t0, 2),
-            "launches": stats["launches"], "hbm_budget_bytes": budget_bytes,
-            "latency_ms": {k: {"p50": round(float(np.percentile(v, 50)), 1), "p99": round(float(np.percentile(v, 99)), 1),
-                                "n": len(v)} for k, v in sorted(lat.items())}}
+    span = prepared[-1]["j"].arrival_s - prepared[0]["j"].arrival_s
+
+    def pct(v):
+        return {"p50": round(float(np.percentile(v, 50)), 1), "p99": round(float(np.percentile(v, 99)), 1)}
+
+    served = total_gates / (t1 - t0)
+    offered = total_gates / span if span > 0 else rate_gates_per_s
+    return {"jobs": len(prepared), "gates": total_gates, "offered_gates_per_s": round(offered, 1),
+            "served_gates_per_s": round(served, 1), "served_over_offered": round(served / offered, 3),
+            "wall_s": round(t1 - t0, 2), "launches": stats["launches"], "hbm_budget_bytes": budget_bytes,
+            "mul32_circuit": "tree accumulation (Sec. V-B-2), 62 levels",
+            "latency_ms": {k: {**pct(v), "n": len(v)} for k, v in sorted(lat.items())},
+            "queue_ms": {k: pct(v) for k, v in sorted(wait.items())},
+            "service_ms": {k: pct(v) for k, v in sorted(serv.items())}}
+
+
+def prepare_config(F, sk, ctx, name, stream):
+    """Encrypted operands resident in HBM and the step of workload `name`."""
+    import torch
+    if name in ("add16", "mul32"):
+        wl = workloads.AddWorkload() if name == "add16" else workloads.MulWorkload()
+        a, b = wl.operands()
+        width, count = wl.width, wl.count
+        ca, cb = sk.encrypt_uint(a, width, nonce=0), sk.encrypt_uint(b, width, nonce=1 << 40)
+        dA, dB = F.to_device(ca), F.to_device(cb)
+        dR = torch.empty_like(dA)
+        kind = "add" if name == "add16" else "mul"
+        fn = F.fhe_add if name == "add16" else F.fhe_mul
+        step = lambda: fn(ctx, dA, dB, dR, count, width, stream)
+        gates, levels, _ = F.fhe_circuit_shape(kind, width)
+        expect = (a + b) % (1 << width) if name == "add16" else (a.astype(object) * b.astype(object)) % (1 << width)
+        label = (f"batched {width}-bit ripple-carry addition" if name == "add16"
+                 else f"batched {width}-bit shift-and-add multiplication (low {width} bits)")
+        workload = {"workload": label, "pairs": count, "width": width, "gates_per_step": gates * count,
+                    "levels": levels}
+        gates_per_step = gates * count
+    else:
+        wl = workloads.MatvecWorkload()
+        M, x = wl.operands()
+        width = wl.width
+        cm = sk.encrypt_uint(M.reshape(-1), width, nonce=0)
+        cx = sk.encrypt_uint(x, width, nonce=1 << 40)
+        dA, dB = F.to_device(cm), F.to_device(cx)
+        dR = torch.empty((wl.rows, width, F.WORDS), dtype=torch.int32, device="cuda")
+        step = lambda: F.fhe_matvec(ctx, dA, dB, dR, wl.rows, wl.cols, width, stream)
+        gates, levels, _ = F.fhe_circuit_shape("matvec", width, wl.rows, wl.cols)
+        expect = (M @ x) % (1 << width)
+        workload = {"workload": f"encrypted {wl.rows}x{wl.cols} matrix-vector product, {width}-bit",
+                    "rows": wl.rows, "cols": wl.cols, "width": width, "gates_per_step": gates, "levels": levels}
+        gates_per_step = gates
+
+    def verify():
+        got = sk.decrypt_uint(F.to_host(dR), width).astype(object)
+        return np.array_equal(got, np.asarray(expect).reshape(-1).astype(object))
+
+    return dict(name=name, step=step, gates_per_step=gates_per_step, levels=levels, workload=workload,
+                verify=verify, dA=dA, dB=dB, dR=dR, width=width)
+
+
+def roofline_of(records):
+    """Roofline object of the blind-rotation shape with the most device time
+    in `records` (per-launch HIP events on the launch stream)."""
+    by_shape = {}
+    for r in records:
+        e = by_shape.setdefault(r["shape"], {"launches": 0, "gates": 0, "ms": 0.0})
+        e["launches"] += 1
+        e["gates"] += r["gates"]
+        e["ms"] += r["blind_rotate_ms"]
+    shape = max(by_shape, key=lambda k: by_shape[k]["ms"])
+    dom = by_shape[shape]
+    gates_per_launch = dom["gates"] / dom["launches"]
+    avg_launch_ms = dom["ms"] / dom["launches"]
+    achieved = LANE_OPS_PER_GATE[shape[2]] * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
+    kernel = f"k_blind_rotate_pair<{shape[2]}>" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}, {shape[2]}>"
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(kernel, gates_per_launch),
+                "kernel": kernel, "launches": dom["launches"], "avg_launch_ms": round(avg_launch_ms, 3),
+                "gates_per_launch": round(gates_per_launch, 1)}
+    per_shape = {f"{k[0]}x{k[1]}/arith{k[2]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
+                 for k, v in sorted(by_shape.items())}
+    return roofline, per_shape, shape
+
+
+def key_switch_roof(records):
+    """Key switching against the aggregate L2 bandwidth: algorithmic bytes =
+    the expected 6,144 non-zero digit rows of 2,004 B gathered per gate."""
+    gates = sum(r["gates"] for r in records)
+    ms = sum(r["key_switch_ms"] for r in records)
+    if not gates or ms <= 0:
+        return None
+    achieved = KS_BYTES_PER_GATE * gates / (ms / 1e3) / 1e12
+    return {"bound": "l2", "achieved": round(achieved, 3), "peak": round(L2_PEAK_TBS, 2), "unit": "TB/s",
+            "frac": round(achieved / L2_PEAK_TBS, 4), "ms": round(ms, 3), "gates": gates}
+
+
+def time_config(F, ctx, cfg, steps, warmup):
+    """Warm-up, then `steps` timed steps with per-launch events."""
+    import torch
+    for _ in range(warmup):
+        cfg["step"]()
+    torch.cuda.synchronize()
+    F.fhe_ctx_timing(ctx)  # drop anything recorded so far
+    F.fhe_ctx_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cfg["step"]()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    F.fhe_ctx_set_timing(ctx, False)
+    records = F.fhe_ctx_timing_launches(ctx)
+    if not cfg["verify"]():
+        raise SystemExit(f"bench: {cfg['name']}: decrypted results differ from plaintext arithmetic")
+    ms = (t1 - t0) * 1e3 / steps
+    roofline, per_shape, shape = roofline_of(records)
+    br = sum(r["blind_rotate_ms"] for r in records)
+    ks = sum(r["key_switch_ms"] for r in records)
+    return {"gates_per_s": round(cfg["gates_per_step"] / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+            "steps": steps, "warmup": warmup, "config": cfg["workload"],
+            "phase_ms_per_step": {"blind_rotate": round(br / steps, 3), "key_switch": round(ks / steps, 3)},
+            "launches_per_step": len(records) // max(steps, 1), "roofline": roofline,
+            "key_switch_roofline": key_switch_roof(records), "timed_by_shape": per_shape,
+            "_shape": shape}
+
+
+def latency(fn, samples):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(samples):
+        s0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - s0)
+    return {"p50_ms": round(1e3 * float(np.median(out)), 2), "p99_ms": round(1e3 * float(np.percentile(out, 99)), 2),
+            "samples": len(out)}
 
 
 def main():
@@ -174,10 +357,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="add16", choices=["add16", "mul32", "matvec"])
-    ap.add_argument("--plain-reps", type=int, default=5)
-    ap.add_argument("--mul-samples", type=int, default=5)
+    ap.add_argument("--config", default="mul32", choices=["add16", "mul32", "matvec"],
+                    help="workload of `value` (default: the 256-pair 32-bit multiplication)")
+    ap.add_argument("--leg-steps", type=int, default=5, help="timed steps of the add16 leg")
+    ap.add_argument("--matvec-steps", type=int, default=1, help="timed steps of the matvec leg (0: skip)")
+    ap.add_argument("--graph-steps", type=int, default=2, help="steps replayed from the captured HIP graphs")
+    ap.add_argument("--plain-reps", type=int, default=50)
+    ap.add_argument("--mul-samples", type=int, default=50)
+    ap.add_argument("--circuit-samples", type=int, default=5)
     ap.add_argument("--cpu-sample-gates", type=int, default=768)
+    ap.add_argument("--cpu-single-gates", type=int, default=48)
     ap.add_argument("--tune-max-width", type=int, default=4096,
                     help="autotune launch shapes up to this batch width before warmup (0 keeps the defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -186,8 +375,11 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load of the serving leg as a fraction of the batched throughput")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--small-budget-jobs", type=int, default=400,
+                    help="jobs of a second serving run under a small HBM budget (0 skips it)")
+    ap.add_argument("--small-budget-mib", type=float, default=256.0)
     ap.add_argument("--goldilocks-steps", type=int, default=1,
-                    help="steps timed once more with the NTT over 2^64 - 2^32 + 1 (0: skip)")
+                    help="add16 steps timed once more with the NTT over 2^64 - 2^32 + 1 (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -198,7 +390,6 @@ def main():
 
     import torch
     import paper_2005_01945_amd as F
-    import workloads
 
     sk, ck = F.fhe_keygen(0)
     ctx = F.Context(ck, 0)
@@ -212,137 +403,82 @@ def main():
     shapes = [[1 << b, *F.fhe_ctx_launch_config(ctx, 1 << b)] for b in range(16)]
     log(f"launch shapes [bucket width, waves/gate, gates/group, arith]: {shapes}")
 
-    if args.config == "add16":
-        wl = workloads.AddWorkload()
-        a, b = wl.operands()
-        width, count = wl.width, wl.count
-        ca, cb = sk.encrypt_uint(a, width, nonce=0), sk.encrypt_uint(b, width, nonce=1 << 40)
-        dA, dB = F.to_device(ca), F.to_device(cb)
-        dR = torch.empty_like(dA)
-        step = lambda: F.fhe_add(ctx, dA, dB, dR, count, width, stream)
-        gates, levels, _ = F.fhe_circuit_shape("add", width)
-        expect = (a + b) % (1 << width)
-        workload = {"workload": f"batched {width}-bit ripple-carry addition", "pairs": count,
-                    "width": width, "gates_per_step": gates * count, "levels": levels}
-    elif args.config == "mul32":
-        wl = workloads.MulWorkload()
-        a, b = wl.operands()
-        width, count = wl.width, wl.count
-        ca, cb = sk.encrypt_uint(a, width, nonce=0), sk.encrypt_uint(b, width, nonce=1 << 40)
-        dA, dB = F.to_device(ca), F.to_device(cb)
-        dR = torch.empty_like(dA)
-        step = lambda: F.fhe_mul(ctx, dA, dB, dR, count, width, stream)
-        gates, levels, _ = F.fhe_circuit_shape("mul", width)
-        expect = (a * b) % (1 << width)
-        workload = {"workload": f"batched {width}-bit shift-and-add multiplication", "pairs": count,
-                    "width": width, "gates_per_step": gates * count, "levels": levels}
-    else:
-        wl = workloads.MatvecWorkload()
-        M, x = wl.operands()
-        width = wl.width
-        cm = sk.encrypt_uint(M.reshape(-1), width, nonce=0)
-        cx = sk.encrypt_uint(x, width, nonce=1 << 40)
-        dA, dB = F.to_device(cm), F.to_device(cx)
-        dR = torch.empty((wl.rows, width, F.WORDS), dtype=torch.int32, device="cuda")
-        step = lambda: F.fhe_matvec(ctx, dA, dB, dR, wl.rows, wl.cols, width, stream)
-        gates, levels, _ = F.fhe_circuit_shape("matvec", width, wl.rows, wl.cols)
-        count = 1
-        expect = (M @ x) % (1 << width)
-        workload = {"workload": f"encrypted {wl.rows}x{wl.cols} matrix-vector product, {width}-bit",
-                    "rows": wl.rows, "cols": wl.cols, "width": width, "gates_per_step": gates, "levels": levels}
-    gates_per_step = gates * count
-
-    log(f"config {args.config}: {gates_per_step} gates/step, {levels} levels; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    F.fhe_ctx_timing(ctx)  # drop anything recorded so far
-    F.fhe_ctx_set_timing(ctx, True)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    F.fhe_ctx_set_timing(ctx, False)
-    records = F.fhe_ctx_timing_launches(ctx)
-    br_ms = sum(r["blind_rotate_ms"] for r in records)
-    ks_ms = sum(r["key_switch_ms"] for r in records)
-    launches = len(records)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = gates_per_step / (ms_per_step / 1e3)
-    log(f"{ms_per_step:.1f} ms/step, {value:.0f} gates/s; blind rotation {br_ms:.1f} ms, "
-        f"key switch {ks_ms:.1f} ms over {launches} launches")
+    # --- the measured workload (`value`) ---
+    main_cfg = prepare_config(F, sk, ctx, args.config, stream)
+    log(f"config {args.config}: {main_cfg['gates_per_step']} gates/step, {main_cfg['levels']} levels; "
+        f"warmup {args.warmup}, timing {args.steps} steps")
+    res = time_config(F, ctx, main_cfg, args.steps, args.warmup)
+    ms_per_step = res["ms_per_step"]
+    value = main_cfg["gates_per_step"] / (ms_per_step / 1e3)
+    log(f"{ms_per_step:.1f} ms/step, {value:.0f} gates/s; phases {res['phase_ms_per_step']}")
 
     # the same steps replayed from the captured HIP graphs (timing off)
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    graph_ms_per_step = (time.perf_counter() - g0) * 1e3 / args.steps
-    log(f"graph replay: {graph_ms_per_step:.1f} ms/step")
+    graph_ms_per_step = None
+    if args.graph_steps > 0:
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            main_cfg["step"]()
+        torch.cuda.synchronize()
+        graph_ms_per_step = (time.perf_counter() - g0) * 1e3 / args.graph_steps
+        log(f"graph replay: {graph_ms_per_step:.1f} ms/step")
 
     # one step with the inputs copied in from pinned host memory and the
     # results copied out (the PCIe-inclusive rate; not `value`)
-    hA = dA.cpu().pin_memory()
-    hB = dB.cpu().pin_memory()
+    dA, dB, dR = main_cfg["dA"], main_cfg["dB"], main_cfg["dR"]
+    hA, hB = dA.cpu().pin_memory(), dB.cpu().pin_memory()
     hR = torch.empty(dR.shape, dtype=dR.dtype).pin_memory()
     torch.cuda.synchronize()
     e0 = time.perf_counter()
     dA.copy_(hA, non_blocking=True)
     dB.copy_(hB, non_blocking=True)
-    step()
+    main_cfg["step"]()
     hR.copy_(dR, non_blocking=True)
     torch.cuda.synchronize()
     e2e_ms = (time.perf_counter() - e0) * 1e3
-    end_to_end = {"gates_per_s": round(gates_per_step / (e2e_ms / 1e3), 1), "ms_per_step": round(e2e_ms, 1),
+    end_to_end = {"gates_per_s": round(main_cfg["gates_per_step"] / (e2e_ms / 1e3), 1), "ms_per_step": round(e2e_ms, 1),
                   "bytes_in": int(hA.numel() + hB.numel()) * 4, "bytes_out": int(hR.numel()) * 4}
     log(f"with host transfers: {end_to_end}")
+    if not main_cfg["verify"]():
+        raise SystemExit("bench: results after the host-transfer step differ from plaintext arithmetic")
+    del hA, hB, hR
 
-    got = sk.decrypt_uint(F.to_host(dR), width)
-    if not np.array_equal(got, np.asarray(expect).reshape(-1).astype(np.uint64)):
-        raise SystemExit("bench: decrypted results differ from plaintext arithmetic")
+    # --- the other batched workloads, each timed with its own roofline ---
+    legs = {}
+    add_cfg = main_cfg if args.config == "add16" else prepare_config(F, sk, ctx, "add16", stream)
+    if args.config != "add16" and args.leg_steps > 0:
+        log(f"leg add16: {add_cfg['gates_per_step']} gates/step, warmup 1, {args.leg_steps} steps")
+        legs["add16"] = time_config(F, ctx, add_cfg, args.leg_steps, 1)
+        log(f"leg add16: {legs['add16']['gates_per_s']} gates/s")
+    if args.config != "matvec" and args.matvec_steps > 0:
+        mv = prepare_config(F, sk, ctx, "matvec", stream)
+        log(f"leg matvec: {mv['gates_per_step']} gates/step, warmup 1, {args.matvec_steps} steps")
+        legs["matvec"] = time_config(F, ctx, mv, args.matvec_steps, 1)
+        log(f"leg matvec: {legs['matvec']['gates_per_s']} gates/s")
+        del mv
+        torch.cuda.empty_cache()
+    if args.config != "mul32" and args.leg_steps > 0:
+        mc = prepare_config(F, sk, ctx, "mul32", stream)
+        log(f"leg mul32: {mc['gates_per_step']} gates/step, warmup 1, 1 step")
+        legs["mul32"] = time_config(F, ctx, mc, 1, 1)
+        del mc
+    for v in legs.values():
+        v.pop("_shape", None)
 
-    # roofline of the dominant kernel (the blind-rotation shape with the most
-    # device time in the timed region), from its launches there
-    by_shape = {}
-    for r in records:
-        e = by_shape.setdefault(r["shape"], {"launches": 0, "gates": 0, "ms": 0.0})
-        e["launches"] += 1
-        e["gates"] += r["gates"]
-        e["ms"] += r["blind_rotate_ms"]
-    shape = max(by_shape, key=lambda k: by_shape[k]["ms"])
-    dom = by_shape[shape]
-    gates_per_launch = dom["gates"] / dom["launches"]
-    avg_launch_ms = dom["ms"] / dom["launches"]
-    achieved = LANE_OPS_PER_GATE[shape[2]] * gates_per_launch / (avg_launch_ms / 1e3) / 1e12
-    dtype = ("u32 (Torus32) / i32 residues mod two 28-bit primes (NTT)" if shape[2] == 1
-             else "u32 (Torus32) / u64 (NTT mod 2^64-2^32+1)")
-    kernel = f"k_blind_rotate_pair<{shape[2]}>" if shape[0] == 2 else f"k_blind_rotate<{shape[1]}, {shape[2]}>"
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(kernel, gates_per_launch),
-                "kernel": kernel, "launches": dom["launches"], "avg_launch_ms": round(avg_launch_ms, 3),
-                "gates_per_launch": round(gates_per_launch, 1)}
-    per_shape = {f"{k[0]}x{k[1]}/arith{k[2]}": {"launches": v["launches"], "gates": v["gates"], "ms": round(v["ms"], 3)}
-                 for k, v in sorted(by_shape.items())}
-
-    # the same step with the NTT over the Goldilocks prime 2^64 - 2^32 + 1 (one
-    # wave per gate, four gates per workgroup), against its own algorithmic
-    # count; then the tuned shapes are put back
+    # the add16 step once more with the NTT over the Goldilocks prime
+    # 2^64 - 2^32 + 1 (one wave per gate, four gates per workgroup), against
+    # its own algorithmic count; then the tuned shapes are put back
     goldilocks = None
     if args.goldilocks_steps > 0:
         saved = [F.fhe_ctx_launch_config(ctx, 1 << b) for b in range(16)]
         F.fhe_ctx_set_launch_config(ctx, 1, 1 << 31, (1, 4, 0))
-        step()
+        add_cfg["step"]()
         torch.cuda.synchronize()
         F.fhe_ctx_timing(ctx)
         F.fhe_ctx_set_timing(ctx, True)
         gs0 = time.perf_counter()
         for _ in range(args.goldilocks_steps):
-            step()
+            add_cfg["step"]()
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - gs0) * 1e3 / args.goldilocks_steps
         F.fhe_ctx_set_timing(ctx, False)
@@ -350,12 +486,12 @@ def main():
         g_gates = sum(r["gates"] for r in grec)
         g_br = sum(r["blind_rotate_ms"] for r in grec)
         g_ach = LANE_OPS_PER_GATE[0] * g_gates / (g_br / 1e3) / 1e12
-        goldilocks = {"gates_per_s": round(gates_per_step / (g_ms / 1e3), 1), "ms_per_step": round(g_ms, 1),
-                      "kernel": "k_blind_rotate<4, 0>", "achieved": round(g_ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                      "unit": "TOP/s", "frac": round(g_ach / VALU_PEAK_TOPS, 4)}
+        goldilocks = {"workload": "add16 x 1024", "gates_per_s": round(add_cfg["gates_per_step"] / (g_ms / 1e3), 1),
+                      "ms_per_step": round(g_ms, 1), "kernel": "k_blind_rotate<4, 0>", "achieved": round(g_ach, 3),
+                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(g_ach / VALU_PEAK_TOPS, 4)}
         for b, shp in enumerate(saved):
             F.fhe_ctx_set_launch_config(ctx, 1 << b, 1 << b, shp)
-        if not np.array_equal(sk.decrypt_uint(F.to_host(dR), width), np.asarray(expect).reshape(-1).astype(np.uint64)):
+        if not add_cfg["verify"]():
             raise SystemExit("bench: Goldilocks-path results differ from plaintext arithmetic")
         log(f"Goldilocks NTT: {goldilocks}")
 
@@ -368,7 +504,7 @@ def main():
         del src, dst
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
 
-    # plain path: one gate per launch, synchronous
+    # plain path: one gate per launch, synchronous (NAND on the four input pairs)
     plain = None
     a_bits, b_bits = workloads.truth_table_inputs()
     p0 = F.to_device(sk.encrypt_bits(a_bits, nonce=1 << 50))
@@ -384,11 +520,12 @@ def main():
     if lat:
         assert list(sk.decrypt_bits(F.to_host(pout))) == [1, 1, 1, 0]
         plain = {"gates_per_s": round(len(lat) / sum(lat), 2), "p50_ms": round(1e3 * float(np.median(lat)), 3),
-                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "gates": len(lat)}
+                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "gates": len(lat),
+                 "reps": args.plain_reps, "batched_over_plain": round(value / (len(lat) / sum(lat)), 1)}
         log(f"plain: {plain}")
 
-    # latency of one 32-bit multiplication: shift-and-add (120 levels) and with
-    # the partial products summed by a tree (62 levels), same 2,824 gates
+    # latency of one 32-bit multiplication: shift-and-add (120 levels), tree
+    # accumulation (62 levels, same 2,824 gates), Karatsuba (full product)
     mul = mul_tree = mul_kara = None
     if args.mul_samples > 0:
         ma = workloads.uniform_uints(11, 1, 32)
@@ -396,47 +533,27 @@ def main():
         mA = F.to_device(sk.encrypt_uint(ma, 32, nonce=1 << 52))
         mB = F.to_device(sk.encrypt_uint(mb, 32, nonce=(1 << 52) + 64))
         mR = torch.empty_like(mA)
-
-        def mul_latency(fn, kind):
-            fn(ctx, mA, mB, mR, 1, 32, stream)
-            torch.cuda.synchronize()
-            ml = []
-            for _ in range(args.mul_samples):
-                s0 = time.perf_counter()
-                fn(ctx, mA, mB, mR, 1, 32, stream)
-                torch.cuda.synchronize()
-                ml.append(time.perf_counter() - s0)
-            assert sk.decrypt_uint(F.to_host(mR), 32)[0] == (int(ma[0]) * int(mb[0])) % (1 << 32)
-            gates, levels, _ = F.fhe_circuit_shape(kind, 32)
-            return {"p50_ms": round(1e3 * float(np.median(ml)), 1),
-                    "p99_ms": round(1e3 * float(np.percentile(ml, 99)), 1),
-                    "samples": len(ml), "gates": gates, "levels": levels}
-
-        mul = mul_latency(F.fhe_mul, "mul")
-        log(f"mul32 latency: {mul}")
-        mul_tree = mul_latency(F.fhe_mul_tree, "mul_tree")
-        log(f"mul32 (tree accumulation) latency: {mul_tree}")
-        # Karatsuba (Sec. III-B-2): all 64 bits of the product
         mR2 = torch.empty((1, 64, mA.shape[-1]), dtype=mA.dtype, device=mA.device)
-        F.fhe_mul_karatsuba(ctx, mA, mB, mR2, 1, 32, stream)
-        torch.cuda.synchronize()
-        kl = []
-        for _ in range(args.mul_samples):
-            s0 = time.perf_counter()
-            F.fhe_mul_karatsuba(ctx, mA, mB, mR2, 1, 32, stream)
-            torch.cuda.synchronize()
-            kl.append(time.perf_counter() - s0)
+        want = (int(ma[0]) * int(mb[0])) % (1 << 32)
+        mul = latency(lambda: F.fhe_mul(ctx, mA, mB, mR, 1, 32, stream), args.mul_samples)
+        assert sk.decrypt_uint(F.to_host(mR), 32)[0] == want
+        mul.update(zip(("gates", "levels"), F.fhe_circuit_shape("mul", 32)[:2]))
+        log(f"mul32 latency: {mul}")
+        mul_tree = latency(lambda: F.fhe_mul_tree(ctx, mA, mB, mR, 1, 32, stream), args.mul_samples)
+        assert sk.decrypt_uint(F.to_host(mR), 32)[0] == want
+        mul_tree.update(zip(("gates", "levels"), F.fhe_circuit_shape("mul_tree", 32)[:2]))
+        log(f"mul32 (tree accumulation) latency: {mul_tree}")
+        mul_kara = latency(lambda: F.fhe_mul_karatsuba(ctx, mA, mB, mR2, 1, 32, stream), args.mul_samples)
         assert sk.decrypt_uint(F.to_host(mR2), 64)[0] == int(ma[0]) * int(mb[0])
-        kg, klv, _ = F.fhe_circuit_shape("karatsuba", 32)
-        mul_kara = {"p50_ms": round(1e3 * float(np.median(kl)), 1), "p99_ms": round(1e3 * float(np.percentile(kl, 99)), 1),
-                    "samples": len(kl), "gates": kg, "levels": klv, "product_bits": 64}
+        mul_kara.update(zip(("gates", "levels"), F.fhe_circuit_shape("karatsuba", 32)[:2]))
+        mul_kara["product_bits"] = 64
         log(f"mul32 Karatsuba (64-bit product) latency: {mul_kara}")
 
     # latency of other circuits of the paper, one instance each: the 16-bit
-    # adders (ripple carry, eqs. (1)-(2); number-wise, GPU_n) and the 4 x 4
-    # 16-bit matrix product by Cannon's algorithm
+    # adders (ripple carry, eqs. (1)-(2); full-adder gates; number-wise, GPU_n)
+    # and the 4 x 4 16-bit matrix product by Cannon's algorithm
     circuits = None
-    if args.mul_samples > 0:
+    if args.circuit_samples > 0:
         ca = workloads.uniform_uints(13, 1, 16)
         cb = workloads.uniform_uints(14, 1, 16)
         cA = F.to_device(sk.encrypt_uint(ca, 16, nonce=(1 << 52) + 128))
@@ -448,73 +565,77 @@ def main():
         dMA = F.to_device(sk.encrypt_uint(MA.reshape(-1), 16, nonce=(1 << 52) + 1024))
         dMB = F.to_device(sk.encrypt_uint(MB.reshape(-1), 16, nonce=(1 << 52) + 2048))
         dMC = torch.empty_like(dMA)
-        legs = {"add16": (lambda: F.fhe_add(ctx, cA, cB, cR, 1, 16, stream), ("add", 16, 0)),
-                "add16_full_adder_gates": (lambda: F.fhe_add_fa(ctx, cA, cB, cR, 1, 16, stream), ("add_fa", 16, 0)),
-                "add16_numberwise": (lambda: F.fhe_add_numberwise(ctx, cA, cB, cR, 1, 16, stream),
-                                     ("add_numberwise", 16, 0)),
-                "matmul4x4_16": (lambda: F.fhe_matmul(ctx, dMA, dMB, dMC, 4, 16, stream), ("matmul", 16, 4))}
+        cl = {"add16": (lambda: F.fhe_add(ctx, cA, cB, cR, 1, 16, stream), ("add", 16, 0)),
+              "add16_full_adder_gates": (lambda: F.fhe_add_fa(ctx, cA, cB, cR, 1, 16, stream), ("add_fa", 16, 0)),
+              "add16_numberwise": (lambda: F.fhe_add_numberwise(ctx, cA, cB, cR, 1, 16, stream),
+                                   ("add_numberwise", 16, 0)),
+              "matmul4x4_16": (lambda: F.fhe_matmul(ctx, dMA, dMB, dMC, 4, 16, stream), ("matmul", 16, 4))}
         circuits = {}
-        for name, (fn, shape) in legs.items():
-            fn()
-            torch.cuda.synchronize()
-            tl = []
-            for _ in range(args.mul_samples):
-                s0 = time.perf_counter()
-                fn()
-                torch.cuda.synchronize()
-                tl.append(time.perf_counter() - s0)
-            g, lv, _ = F.fhe_circuit_shape(shape[0], shape[1], shape[2])
-            circuits[name] = {"p50_ms": round(1e3 * float(np.median(tl)), 1), "gates": g, "levels": lv}
+        for name, (fn, shape) in cl.items():
+            r = latency(fn, args.circuit_samples)
+            r.update(zip(("gates", "levels"), F.fhe_circuit_shape(shape[0], shape[1], shape[2])[:2]))
+            circuits[name] = r
         assert sk.decrypt_uint(F.to_host(cR), 16)[0] == (int(ca[0]) + int(cb[0])) % (1 << 16)
         got = sk.decrypt_uint(F.to_host(dMC).reshape(16, 16, -1), 16).reshape(4, 4).astype(object)
         assert (got == (MA.astype(object) @ MB.astype(object)) % (1 << 16)).all()
+        # the 1024 add16 pairs through full-adder gates (MAJ, XOR3): additions
+        # per second against the two-input circuit's
+        wl = workloads.AddWorkload()
+        aA, aB, aR = add_cfg["dA"], add_cfg["dB"], add_cfg["dR"]
+        fa = latency(lambda: F.fhe_add_fa(ctx, aA, aB, aR, wl.count, wl.width, stream), 1)
+        assert add_cfg["verify"]()
+        g_fa = F.fhe_circuit_shape("add_fa", wl.width)[0] * wl.count
+        add_ms = legs["add16"]["ms_per_step"] if "add16" in legs else ms_per_step if args.config == "add16" else None
+        circuits["add16_x1024_batched"] = {
+            "two_input_gates": None if add_ms is None else {"ms": add_ms, "adds_per_s": round(wl.count / (add_ms / 1e3), 1)},
+            "full_adder_gates": {"ms": fa["p50_ms"], "adds_per_s": round(wl.count / (fa["p50_ms"] / 1e3), 1),
+                                 "gates": g_fa, "gates_per_s": round(g_fa / (fa["p50_ms"] / 1e3), 1)}}
         log(f"circuit latency: {circuits}")
-        if args.config == "add16":
-            # the benchmark's 1024 add16 pairs through full-adder gates (MAJ,
-            # XOR3): additions per second against the two-input circuit's
-            F.fhe_add_fa(ctx, dA, dB, dR, count, width, stream)
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            F.fhe_add_fa(ctx, dA, dB, dR, count, width, stream)
-            torch.cuda.synchronize()
-            fa_s = time.perf_counter() - s0
-            assert (sk.decrypt_uint(F.to_host(dR), width) == (wl.operands()[0] + wl.operands()[1]) % (1 << width)).all()
-            g_fa = F.fhe_circuit_shape("add_fa", width)[0] * count
-            circuits["add16_x1024_batched"] = {
-                "two_input_gates": {"ms": round(ms_per_step, 1), "adds_per_s": round(count / (ms_per_step / 1e3), 1)},
-                "full_adder_gates": {"ms": round(1e3 * fa_s, 1), "adds_per_s": round(count / fa_s, 1),
-                                     "gates": g_fa, "gates_per_s": round(g_fa / fa_s, 1)}}
-            log(f"add16 x 1024 batched: {circuits['add16_x1024_batched']}")
+    del add_cfg
 
     serving = None
     if args.serve_jobs > 0:
-        log(f"serving: {args.serve_jobs} jobs at {args.serve_load:.2f} x {value:.0f} gates/s")
+        log(f"serving: {args.serve_jobs} jobs at {args.serve_load:.2f} x {value:.0f} gates/s ({args.config})")
         serving = serving_leg(F, sk, ctx, args.serve_load * value, args.serve_jobs,
                               int(args.serve_budget_gib * (1 << 30)))
+        serving["offered_as"] = f"{args.serve_load} x the batched {args.config} rate"
         log(f"serving: {serving}")
+    if args.serve_jobs > 0 and args.small_budget_jobs > 0:
+        log(f"serving under a {args.small_budget_mib:.0f} MiB budget: {args.small_budget_jobs} jobs")
+        small = serving_leg(F, sk, ctx, args.serve_load * value, args.small_budget_jobs,
+                            int(args.small_budget_mib * (1 << 20)), seed=5)
+        serving["small_budget"] = small
+        log(f"serving, small budget: {small}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(sk, workloads.AddWorkload().operands()[0], workloads.AddWorkload().operands()[1],
-                           16, args.cpu_sample_gates)
+        full = {"add16 x 1024": F.fhe_circuit_shape("add", 16)[0] * 1024,
+                "mul32 x 256": F.fhe_circuit_shape("mul", 32)[0] * 256,
+                "matvec 64x64": F.fhe_circuit_shape("matvec", 16, 64, 64)[0]}
+        cpu = cpu_baseline(sk, args.config, args.cpu_sample_gates, args.cpu_single_gates, full)
         log(f"cpu baseline: {cpu}")
 
+    shape = res.pop("_shape")
+    dtype = ("u32 (Torus32) / i32 residues mod two 28-bit primes (NTT)" if shape[2] == 1
+             else "u32 (Torus32) / u64 (NTT mod 2^64-2^32+1)")
     line = {
         "metric": "bootstrapped gates/sec on 1 MI355X (batched vs plain) + p50/p99 latency per 32-bit mul",
         "value": round(value, 1), "unit": "gates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "graph_ms_per_step": round(graph_ms_per_step, 3),
+        "ms_per_step": round(ms_per_step, 3),
+        "graph_ms_per_step": None if graph_ms_per_step is None else round(graph_ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": workload,
+        "config": main_cfg["workload"],
         "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
-        "mul32_karatsuba_latency": mul_kara, "circuit_latency": circuits, "goldilocks_ntt": goldilocks,
-        "with_host_transfers": end_to_end,
+        "mul32_karatsuba_latency": mul_kara, "batched_legs": legs, "circuit_latency": circuits,
+        "goldilocks_ntt": goldilocks, "with_host_transfers": end_to_end,
         "serving": serving,
-        "phase_ms_per_step": {"blind_rotate": round(br_ms / args.steps, 3), "key_switch": round(ks_ms / args.steps, 3)},
+        "phase_ms_per_step": res["phase_ms_per_step"],
+        "key_switch_roofline": res["key_switch_roofline"],
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
-                          "timed_by_shape": per_shape},
-        "roofline": roofline, "cpu_baseline": cpu,
+                          "timed_by_shape": res["timed_by_shape"]},
+        "roofline": res["roofline"], "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -34,7 +34,14 @@
  *    enqueued.  Functions without a stream take HOST buffers and complete
  *    before returning.
  *  - Inputs and outputs of one call must not overlap.
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time.  Its calls may use
+ *    different streams: each call's device work is ordered after the
+ *    context's previous call on another stream (an event wait), because
+ *    calls share the context's scratch buffer and circuit pools.
+ *  - Gate codes in device memory cannot be checked when a call is made.  A
+ *    gate whose code is not valid for its call outputs the all-zero sample,
+ *    and the next batched call on the context made after that work has
+ *    completed (or fhe_ctx_check) returns FHE_EINVAL.
  */
 #ifndef FHE_H
 #define FHE_H
@@ -168,10 +175,10 @@ void fhe_ctx_destroy(fhe_ctx* ctx);
  * vector, sample extraction and key switching, all gates of the batch in one
  * launch per step.  ops: device uint8[count]; in0, in1, out: device
  * uint32[count][n+1].  count = 0 is a no-op.  The result is bit-exact with
- * the definition (exact NTT arithmetic).  The codes live in device memory and
- * are not checked on the host: a code outside FHE_AND..FHE_ORYN (including
- * the three-input codes, which need fhe_bootstrap_gate3_batch) computes
- * FHE_ORYN. */
+ * the definition (exact NTT arithmetic).  The codes live in device memory: a
+ * code outside FHE_AND..FHE_ORYN (including the three-input codes, which need
+ * fhe_bootstrap_gate3_batch) gives the all-zero output sample and is reported
+ * as FHE_EINVAL by the context's next batched call or fhe_ctx_check. */
 int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0,
                              const uint32_t* in1, uint32_t* out, size_t count, void* stream);
 
@@ -181,6 +188,27 @@ int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* i
  * MAJ: c1 + c2 + c3, XOR3: -2 (c1 + c2 + c3), then the same bootstrap. */
 int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
                               const uint32_t* in2, uint32_t* out, size_t count, void* stream);
+
+/* Compound gates (Sec. V-A-3: two gates on the same inputs computed
+ * together), here from ONE blind rotation: out0[g] = ops0[g](in0[g], in1[g])
+ * and out1[g] = ops1[g](in0[g], in1[g]) for symmetric codes (FHE_AND, NAND,
+ * OR, NOR, XOR, XNOR).  The rotation takes the phase of c1 + c2 (-1/4, 0,
+ * +1/4 for 0, 1, 2 true inputs, no constant) through the constant test
+ * vector 1/16; coefficients 3N/4 and N/4 of the result are extracted (E1,
+ * E2) and a gate with values g_k (+1 true, -1 false, k true inputs) is the
+ * sample (g1 - g2) E1 + (g1 - g0) E2 + (0, (g0 + g2)/16), key-switched.  One
+ * rotation and two key switchings per gate pair instead of two of each; the
+ * words differ from the single gates' (other samples) and decrypt the same.
+ * ops0, ops1: device uint8[count]; in0, in1, out0, out1: device
+ * uint32[count][n+1].  A code that is not symmetric gives all-zero outputs
+ * and is reported like an invalid code of fhe_bootstrap_gate_batch. */
+int fhe_bootstrap_compound_batch(fhe_ctx* ctx, const uint8_t* ops0, const uint8_t* ops1, const uint32_t* in0,
+                                 const uint32_t* in1, uint32_t* out0, uint32_t* out1, size_t count, void* stream);
+
+/* FHE_EINVAL (and clears the report) if a kernel of this context met an
+ * invalid gate code since the last report; FHE_OK otherwise.  Synchronize
+ * the stream of the work in question first. */
+int fhe_ctx_check(fhe_ctx* ctx);
 
 /* Programmable bootstrapping: out[g] = the bootstrapped and key-switched
  * sample of in[g] with the test vector tv (device uint32[N]) in place of the
@@ -214,6 +242,15 @@ int fhe_add(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, siz
  * levels).  Buffers and errors as fhe_add. */
 int fhe_add_fa(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
                uint32_t width, void* stream);
+
+/* R = (A + B) mod 2^width, the ripple-carry adder of fhe_add with compound
+ * gates (Sec. V-A-3): the XOR and the AND of the same two bits come from one
+ * rotation (fhe_bootstrap_compound_batch), three rotations per middle bit
+ * instead of five (16 bits: 45 rotations in 30 levels against 74 gates).
+ * Levels are ASAP (not balanced).  Output words differ from fhe_add's;
+ * buffers and errors as fhe_add. */
+int fhe_add_compound(fhe_ctx* ctx, const uint32_t* A, const uint32_t* B, uint32_t* R, size_t count,
+                     uint32_t width, void* stream);
 
 /* R = (A + B) mod 2^width by number-wise addition (GPU_n, Sec. V-B-1): w rounds
  * of carry = R & B, R = R ^ B, B = carry << 1 over all bits at once (the
@@ -338,7 +375,8 @@ int fhe_ctx_set_launch_config(fhe_ctx* ctx, uint32_t min_width, uint32_t max_wid
 /* Number of gates and of levels of a circuit as the library schedules it
  * (kind 0 = add, 1 = mul, 2 = matvec, 3 = mul with tree accumulation,
  * 4 = Karatsuba, 5 = number-wise add, 6 = Cannon matmul with rows = n,
- * 7 = full-adder add; rows/cols only for matvec and matmul). */
+ * 7 = full-adder add, 8 = compound add; rows/cols only for matvec and
+ * matmul).  A compound gate counts once (one bootstrap). */
 int fhe_circuit_shape(int kind, uint32_t width, uint32_t rows, uint32_t cols,
                       uint64_t* gates, uint32_t* levels, uint64_t* widest_level);
 
@@ -362,6 +400,8 @@ int fhe_circuit_schedule(int kind, uint32_t width, uint32_t rows, uint32_t cols,
 /* outputs to the caller's buffer.  Jobs that arrive while a tick runs join */
 /* the next tick.  Results do not depend on the mix (each gate is computed  */
 /* exactly, independently of the others in its launch).                      */
+/* Ticks are enqueued ahead of the device (up to three in flight), so the    */
+/* GPU does not idle between them; a job is done once its last tick ran.     */
 /* ---------------------------------------------------------------------- */
 typedef struct fhe_server fhe_server;
 
@@ -404,6 +444,11 @@ int fhe_serve_submit(fhe_server* srv, const fhe_job* job, uint64_t* ticket);
  * completion in milliseconds (-1 before).  Returns FHE_ECANCELED or the
  * job's error code for cancelled or failed jobs. */
 int fhe_serve_poll(fhe_server* srv, uint64_t ticket, int* state, double* latency_ms);
+
+/* Split of a done job's latency: time queued before admission and time from
+ * admission to completion (milliseconds; either pointer may be NULL).
+ * EINVAL: unknown ticket or a job that is not done. */
+int fhe_serve_job_times(fhe_server* srv, uint64_t ticket, double* queue_ms, double* service_ms);
 
 /* Blocks until the job is done, cancelled or failed, or timeout_s elapses
  * (FHE_EBUSY). */
@@ -457,6 +502,31 @@ const char* fhe_last_error(void);
  *   acc[2][N] <- acc + BK_i [x] (X^abar acc - acc),
  * bk_i: uint32 [2l][2][N] (coefficient domain, rows r = 2j + p). */
 int fhe_debug_cmux(int device, int arith, const uint32_t* bk_i, int32_t abar, uint32_t* acc);
+
+/* Test entries: the level schedule of the plan a circuit entry point runs on
+ * this context, and the words its wires hold after a run, so that tests can
+ * recompute sampled gates of a full-size circuit from the inputs the GPU gave
+ * them (the wire ids travel with the gates, so every gate can be checked on
+ * its own).  kind as in fhe_circuit_shape; count = 1 for matvec (rows, cols)
+ * and matmul (rows = n); other kinds ignore rows and cols.  The plan is built
+ * (and its pool allocated) if the context has none yet.
+ * fhe_debug_plan: gates_out (host, NULL to query sizes) receives
+ * [gates][5] uint32 {op, in0, in1, out, in2} in launch order, in2 =
+ * 0xFFFFFFFF for two-input gates; a compound gate has op = 0x10000 | code0 |
+ * code1 << 8 and in2 = the wire of its second output; level_off (host, NULL allowed) receives
+ * levels + 1 offsets into that list; *n_gates, *n_levels the sizes.  A wire
+ * id is (region << 30) | index, region 0 = A, 1 = B, 2 = R (the caller's
+ * buffers of the entry point), 3 = the plan's pool; sample `index` of the
+ * region.  fhe_debug_read_wires waits for the device, then copies the n
+ * wires' samples to words_out (host [n][n+1]); A, B, R are the buffers the
+ * entry point ran on.  EINVAL: bad kind or sizes, buffers too small, a wire
+ * outside the plan's regions. */
+int fhe_debug_plan(fhe_ctx* ctx, int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t count,
+                   uint32_t* gates_out, uint64_t max_gates, uint32_t* level_off, uint32_t max_levels,
+                   uint64_t* n_gates, uint32_t* n_levels);
+int fhe_debug_read_wires(fhe_ctx* ctx, int kind, uint32_t width, uint32_t rows, uint32_t cols, uint64_t count,
+                         const uint32_t* A, const uint32_t* B, const uint32_t* R, const uint32_t* wires, size_t n,
+                         uint32_t* words_out);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,9 @@ FHE_OK, FHE_EINVAL, FHE_ENOMEM, FHE_EDEVICE, FHE_EBUSY, FHE_ECANCELED, FHE_EIO =
 AND, NAND, OR, NOR, XOR, XNOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
 MAJ, XOR3 = 10, 11  # three-input gates (fhe_bootstrap_gate3_batch, circuits)
 WORDS = 501  # n + 1 words per LWE sample
+# circuit kinds of fhe_circuit_shape / fhe_circuit_schedule / fhe_debug_plan
+CIRCUIT_KINDS = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5,
+                 "matmul": 6, "add_fa": 7, "add_compound": 8}
 
 
 class FheError(RuntimeError):
@@ -72,6 +75,9 @@ _SIGS = {
     "fhe_add_fa": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_bootstrap_gate3_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_bootstrap_lut_batch": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_bootstrap_compound_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_ctx_check": (C.c_int, [_vp]),
+    "fhe_add_compound": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
     "fhe_circuit_create": (C.c_int, [_vp, _vp, C.c_uint32, C.c_uint32, _vp, C.c_uint32, C.POINTER(_vp)]),
     "fhe_circuit_run": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
@@ -94,12 +100,17 @@ _SIGS = {
     "fhe_serve_submit": (C.c_int, [_vp, _vp, C.POINTER(C.c_uint64)]),
     "fhe_serve_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "fhe_serve_wait": (C.c_int, [_vp, C.c_uint64, C.c_double]),
+    "fhe_serve_job_times": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fhe_serve_cancel": (C.c_int, [_vp, C.c_uint64]),
     "fhe_serve_stats": (C.c_int, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "fhe_serve_destroy": (None, [_vp]),
     "fhe_last_error": (C.c_char_p, []),
     "fhe_debug_cmux": (C.c_int, [C.c_int, C.c_int, _vp, C.c_int32, _vp]),
+    "fhe_debug_plan": (C.c_int, [_vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _vp, C.c_uint64,
+                                 _vp, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]),
+    "fhe_debug_read_wires": (C.c_int, [_vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _vp, _vp, _vp,
+                                       _vp, C.c_size_t, _vp]),
 }
 
 _lib = None
@@ -303,6 +314,23 @@ def fhe_bootstrap_lut_batch(ctx, tv, inp, out, count, stream=None):
            "fhe_bootstrap_lut_batch")
 
 
+def fhe_bootstrap_compound_batch(ctx, ops0, ops1, in0, in1, out0, out1, count, stream=None):
+    """(out0, out1) = (ops0(in0, in1), ops1(in0, in1)) from one blind rotation per gate pair."""
+    _check(lib().fhe_bootstrap_compound_batch(ctx.h, _dev(ops0), _dev(ops1), _dev(in0), _dev(in1), _dev(out0),
+                                              _dev(out1), count, _stream(stream)), "fhe_bootstrap_compound_batch")
+
+
+def fhe_ctx_check(ctx):
+    """Raises FheError(FHE_EINVAL) if a kernel met an invalid gate code since the last check."""
+    _check(lib().fhe_ctx_check(ctx.h), "fhe_ctx_check")
+
+
+def fhe_add_compound(ctx, A, B, R, count, width, stream=None):
+    """R = (A + B) mod 2^width, ripple carry with compound (XOR, AND) gates."""
+    _check(lib().fhe_add_compound(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)),
+           "fhe_add_compound")
+
+
 def fhe_add_numberwise(ctx, A, B, R, count, width, stream=None):
     _check(lib().fhe_add_numberwise(ctx.h, _dev(A), _dev(B), _dev(R), count, width, _stream(stream)),
            "fhe_add_numberwise")
@@ -334,8 +362,7 @@ def fhe_matmul(ctx, A, B, Cm, n, width, stream=None):
 
 def fhe_circuit_schedule(kind, width, count, cu_count=256, rows=0, cols=0):
     """Gates per launch of the level schedule for `count` instances."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6,
-         "add_fa": 7}[kind]
+    k = CIRCUIT_KINDS[kind]
     lv = C.c_uint32()
     _check(lib().fhe_circuit_schedule(k, width, rows, cols, count, cu_count, None, 0, C.byref(lv)),
            "fhe_circuit_schedule")
@@ -348,8 +375,7 @@ def fhe_circuit_schedule(kind, width, count, cu_count=256, rows=0, cols=0):
 def fhe_circuit_shape(kind, width, rows=0, cols=0):
     """(gates, levels, widest level) of a circuit; kind in {'add', 'mul', 'matvec', 'mul_tree',
     'karatsuba', 'add_numberwise', 'matmul', 'add_fa'} (matmul: rows = n)."""
-    k = {"add": 0, "mul": 1, "matvec": 2, "mul_tree": 3, "karatsuba": 4, "add_numberwise": 5, "matmul": 6,
-         "add_fa": 7}[kind]
+    k = CIRCUIT_KINDS[kind]
     g, lv, wd = C.c_uint64(), C.c_uint32(), C.c_uint64()
     _check(lib().fhe_circuit_shape(k, width, rows, cols, C.byref(g), C.byref(lv), C.byref(wd)),
            "fhe_circuit_shape")
@@ -485,6 +511,13 @@ def fhe_serve_wait(srv, ticket, timeout_s=600.0):
     _check(lib().fhe_serve_wait(srv.h, ticket, timeout_s), "fhe_serve_wait")
 
 
+def fhe_serve_job_times(srv, ticket):
+    """(queue_ms, service_ms) of a done job."""
+    q, v = C.c_double(), C.c_double()
+    _check(lib().fhe_serve_job_times(srv.h, ticket, C.byref(q), C.byref(v)), "fhe_serve_job_times")
+    return q.value, v.value
+
+
 def fhe_serve_cancel(srv, ticket):
     _check(lib().fhe_serve_cancel(srv.h, ticket), "fhe_serve_cancel")
 
@@ -502,6 +535,29 @@ def fhe_debug_cmux(bk_i, abar, acc, device=0, arith=0):
     a = np.ascontiguousarray(acc, np.uint32).copy()
     _check(lib().fhe_debug_cmux(device, arith, pb, abar, a.ctypes.data), "fhe_debug_cmux")
     return a
+
+
+def fhe_debug_plan(ctx, kind, width, count=1, rows=0, cols=0):
+    """(gates [G][5] uint32 {op, in0, in1, out, in2}, level offsets [L+1]) of
+    the plan a circuit entry point runs (test entry)."""
+    k = CIRCUIT_KINDS[kind]
+    g, lv = C.c_uint64(), C.c_uint32()
+    _check(lib().fhe_debug_plan(ctx.h, k, width, rows, cols, count, None, 0, None, 0, C.byref(g), C.byref(lv)),
+           "fhe_debug_plan")
+    gates = np.zeros((g.value, 5), np.uint32)
+    off = np.zeros(lv.value + 1, np.uint32)
+    _check(lib().fhe_debug_plan(ctx.h, k, width, rows, cols, count, gates.ctypes.data, g.value, off.ctypes.data,
+                                lv.value + 1, C.byref(g), C.byref(lv)), "fhe_debug_plan")
+    return gates, off
+
+
+def fhe_debug_read_wires(ctx, kind, width, A, B, R, wires, count=1, rows=0, cols=0):
+    """Samples [n][n+1] on the given wires of a plan after a run on A, B, R (test entry)."""
+    w, pw = _host(wires, np.uint32)
+    out = np.zeros((w.shape[0], WORDS), np.uint32)
+    _check(lib().fhe_debug_read_wires(ctx.h, CIRCUIT_KINDS[kind], width, rows, cols, count, _dev(A), _dev(B),
+                                      _dev(R), pw, w.shape[0], out.ctypes.data), "fhe_debug_read_wires")
+    return out
 
 
 # ---------------------------------------------------------------------------

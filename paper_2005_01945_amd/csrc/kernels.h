@@ -11,11 +11,24 @@ namespace dev {
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = 64 * kWavesPerBlock;
 
+// Compound gates: two symmetric gates of the same two inputs from one blind
+// rotation.  In descriptor mode the op field holds kCompoundFlag | code0 |
+// code1 << 8 and desc3[g] the wire of the second output.
+constexpr uint32_t kCompoundFlag = 1u << 16;
+
 // Where a batch of gates reads its operands and writes its results.
 //  Direct mode (desc == nullptr): gate g reads in0 + g*(n+1), in1 + g*(n+1),
 //  writes out + g*(n+1); its code is ops[g], or op_const when ops == nullptr.
+//  With ops1 (compound batch) gate g is the compound of codes ops[g] and
+//  ops1[g], its second output out1 + g*(n+1).
 //  Descriptor mode: desc[g] = {op, in0 wire, in1 wire, out wire}; a wire id
 //  is (region << 30) | index and addresses region[region] + index*(n+1).
+//  pair_slots = 1: every gate owns two extracted-sample slots (2g, 2g+1) and
+//  key switching runs over 2*count samples (compound gates present); slot
+//  2g+1 of a gate that is not compound is skipped.
+//  A gate whose code is not valid for the batch (two-input codes 0..9; MAJ
+//  and XOR3 with a third input; symmetric codes for compound gates) outputs
+//  the all-zero sample and stores 0x100 | code into *err (when err is set).
 struct GateIO {
     const uint4* desc;        // {op, in0, in1, out} wire ids per gate, or null
     const uint32_t* desc3;    // with desc: third-input wire id per gate (three-input codes), or null
@@ -27,6 +40,10 @@ struct GateIO {
     const uint32_t* tv;       // programmable bootstrapping: test vector [N] (in0 taken as is), or null
     uint32_t* out;
     uint32_t* region[4];
+    const uint8_t* ops1;      // compound batch (direct mode): second code per gate, or null
+    uint32_t* out1;           //   and its outputs [count][n+1]
+    uint32_t pair_slots;      // 1: two extracted-sample slots per gate
+    uint32_t* err;            // invalid-code report word (device-visible), or null
 };
 
 // Per-context device key material.
@@ -64,11 +81,13 @@ struct LaunchConfig {
     uint32_t arith;
 };
 
-// Gate prologue + blind rotation + sample extraction: writes big[g][N+1].
+// Gate prologue + blind rotation + sample extraction: writes big[g][N+1]
+// (big[2g], big[2g+1] with pair_slots).
 hipError_t launch_blind_rotate(const DeviceKeys& K, const GateIO& io, uint32_t* big,
                                uint32_t count, LaunchConfig cfg, hipStream_t s);
 
-// Key switching big[g] -> the gate's output sample.
+// Key switching big[k] -> the gate's output sample, k < count (with
+// pair_slots, count = 2 * gates).
 hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32_t* big,
                              uint32_t count, hipStream_t s);
 

@@ -739,18 +739,10 @@ struct Arith<1> {
     }
 };
 
-// Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding).
-// Three-input codes (when a third input is present): no constant, all three
-// inputs with weight 1 (majority) or -2 (parity).
-__device__ __forceinline__ void gate_consts(uint32_t op, bool three, uint32_t& kappa, int32_t& s1, int32_t& s2,
-                                            int32_t& s3) {
+// Gate constants: phase offset kappa and input signs (TFHE +-1/8 encoding)
+// of the two-input codes 0..9.
+__device__ __forceinline__ void gate_consts(uint32_t op, uint32_t& kappa, int32_t& s1, int32_t& s2) {
     constexpr uint32_t mu = kMu;
-    s3 = 0;
-    if (three && (op == FHE_MAJ || op == FHE_XOR3)) {
-        kappa = 0;
-        s1 = s2 = s3 = op == FHE_MAJ ? 1 : -2;
-        return;
-    }
     switch (op) {
     case FHE_AND:   kappa = 0u - mu;      s1 = 1;  s2 = 1;  break;
     case FHE_NAND:  kappa = mu;           s1 = -1; s2 = -1; break;
@@ -765,30 +757,87 @@ __device__ __forceinline__ void gate_consts(uint32_t op, bool three, uint32_t& k
     }
 }
 
+// Value (+1 true, -1 false) of a symmetric two-input code with k of its two
+// inputs true; 0 for a code that is not symmetric (compound gates take
+// AND, NAND, OR, NOR, XOR, XNOR).
+__device__ __forceinline__ int32_t sym_value(uint32_t op, int k) {
+    switch (op) {
+    case FHE_AND:  return k == 2 ? 1 : -1;
+    case FHE_NAND: return k == 2 ? -1 : 1;
+    case FHE_OR:   return k >= 1 ? 1 : -1;
+    case FHE_NOR:  return k >= 1 ? -1 : 1;
+    case FHE_XOR:  return k == 1 ? 1 : -1;
+    case FHE_XNOR: return k == 1 ? -1 : 1;
+    default:       return 0;
+    }
+}
+
+// What gate g of a batch computes (uniform over the wave).
+struct GateMode {
+    uint32_t op0, op1;  // code; second code of a compound gate
+    bool compound;      // two symmetric gates from one rotation
+    bool three;         // MAJ / XOR3 with a third input
+    bool valid;
+};
+
+__device__ __forceinline__ GateMode gate_mode(const GateIO& io, uint32_t g) {
+    GateMode m{0u, 0u, false, false, true};
+    if (io.tv) return m;  // programmable bootstrapping: no gate code
+    uint32_t op;
+    bool has3;
+    if (io.desc) {
+        op = io.desc[g].x;
+        has3 = io.desc3 != nullptr;
+        m.compound = (op & kCompoundFlag) != 0;
+    } else {
+        op = io.ops ? io.ops[g] : io.op_const;
+        has3 = io.in2 != nullptr;
+        m.compound = io.ops1 != nullptr;
+    }
+    if (m.compound) {
+        m.op0 = op & 0xFFu;
+        m.op1 = io.desc ? (op >> 8) & 0xFFu : io.ops1[g];
+        m.valid = sym_value(m.op0, 0) != 0 && sym_value(m.op1, 0) != 0 && (!io.desc || op < 2 * kCompoundFlag);
+        return m;
+    }
+    m.op0 = op;
+    m.three = has3 && (op == FHE_MAJ || op == FHE_XOR3);
+    m.valid = op <= FHE_ORYN || m.three;
+    return m;
+}
+
 __device__ __forceinline__ uint32_t* wire_ptr(const GateIO& io, uint32_t w) {
     return io.region[w >> 30] + (size_t)(w & 0x3FFFFFFFu) * NW;
 }
 
-// c3 is null for a two-input gate.
-__device__ __forceinline__ void gate_operands(const GateIO& io, uint32_t g, uint32_t& op,
+// Input samples of gate g; c3 is null unless the gate takes three inputs.
+__device__ __forceinline__ void gate_operands(const GateIO& io, uint32_t g, const GateMode& m,
                                               const uint32_t*& c1, const uint32_t*& c2, const uint32_t*& c3) {
     c3 = nullptr;
     if (io.desc) {
         const uint4 d = io.desc[g];
-        op = d.x;
         c1 = wire_ptr(io, d.y);
         c2 = wire_ptr(io, d.z);
-        if (io.desc3 && (op == FHE_MAJ || op == FHE_XOR3)) c3 = wire_ptr(io, io.desc3[g]);
+        if (m.three) c3 = wire_ptr(io, io.desc3[g]);
     } else {
-        op = io.ops ? io.ops[g] : io.op_const;
         c1 = io.in0 + (size_t)g * NW;
         c2 = io.in1 + (size_t)g * NW;
-        if (io.in2 && (op == FHE_MAJ || op == FHE_XOR3)) c3 = io.in2 + (size_t)g * NW;
+        if (m.three) c3 = io.in2 + (size_t)g * NW;
     }
 }
 
 __device__ __forceinline__ uint32_t* gate_output(const GateIO& io, uint32_t g) {
     return io.desc ? wire_ptr(io, io.desc[g].w) : io.out + (size_t)g * NW;
+}
+
+// Output of key-switched sample k: gate k, or with pair slots output k & 1
+// of gate k >> 1 (null for the unused second slot of a single gate).
+__device__ __forceinline__ uint32_t* ks_output(const GateIO& io, uint32_t k) {
+    if (!io.pair_slots) return gate_output(io, k);
+    const uint32_t g = k >> 1;
+    if ((k & 1) == 0) return gate_output(io, g);
+    if (io.desc) return (io.desc[g].x & kCompoundFlag) ? wire_ptr(io, io.desc3[g]) : nullptr;
+    return io.ops1 ? io.out1 + (size_t)g * NW : nullptr;
 }
 
 template <int THREADS, class L>
@@ -801,20 +850,21 @@ __device__ __forceinline__ void load_twiddles(L& S, const uint64_t* twf, const u
 }
 
 // Gate linear combination and modulus switch to Z_2N.  Lane l keeps abar of
-// words l + 64k in ab[k]; returns bbar (uniform).
+// words l + 64k in ab[k]; returns bbar (uniform).  Two-input codes: (0,
+// kappa) + s1 c1 + s2 c2; MAJ: c1 + c2 + c3; XOR3: -2 (c1 + c2 + c3);
+// compound gates: c1 + c2; programmable bootstrapping: c1 itself.
 __device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int lane, uint32_t (&ab)[8]) {
-    uint32_t op;
+    const GateMode m = gate_mode(io, g);
     const uint32_t *c1, *c2, *c3;
-    gate_operands(io, g, op, c1, c2, c3);
-    uint32_t kappa;
-    int32_t s1, s2, s3;
-    gate_consts(op, c3 != nullptr, kappa, s1, s2, s3);
-    if (io.tv) {  // programmable bootstrapping: the input sample itself
-        s1 = 1;
-        s2 = s3 = 0;
-        kappa = 0;
-        c2 = c1;
-        c3 = nullptr;
+    gate_operands(io, g, m, c1, c2, c3);
+    uint32_t kappa = 0;
+    int32_t s1 = 1, s2 = 1, s3 = 0;
+    if (io.tv) {
+        s2 = 0;
+    } else if (m.three) {
+        s1 = s2 = s3 = m.op0 == FHE_MAJ ? 1 : -2;
+    } else if (!m.compound) {
+        gate_consts(m.op0, kappa, s1, s2);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -830,12 +880,18 @@ __device__ __forceinline__ int gate_prologue(const GateIO& io, uint32_t g, int l
     return __builtin_amdgcn_readlane(ab[7], NLWE - 448);
 }
 
+// Constant test vector of gate g: mu = 1/8 for the gates, 1/16 for compound
+// gates (their two outputs are weighted sums of two extractions).
+__device__ __forceinline__ uint32_t gate_mu(const GateIO& io, uint32_t g) {
+    return gate_mode(io, g).compound ? kMu >> 1 : kMu;
+}
+
 // Test-vector rotation: ACC = (0, X^(2N - bbar) v), v = mu (1 + X + ... +
 // X^(N-1)).  Lane l = 32h + t writes coefficients t + 32q of polynomial h.
 // With a test vector tv (programmable bootstrapping): ACC = (0, X^c tv),
 // coefficient m = tv[j] for j = (m - c) mod 2N < N, else -tv[j - N].
 __device__ __forceinline__ void acc_init(uint32_t (&acc)[2][1024], int bbar, int h, int t,
-                                         const uint32_t* __restrict__ tv) {
+                                         const uint32_t* __restrict__ tv, uint32_t mu) {
     const int c = (2 * N - bbar) & (2 * N - 1);
     if (tv) {
 #pragma unroll
@@ -853,7 +909,7 @@ __device__ __forceinline__ void acc_init(uint32_t (&acc)[2][1024], int bbar, int
     for (int q = 0; q < 32; ++q) {
         const int m = t + 32 * q;
         const uint32_t sgn = (m >= cm) ? neg : 1u - neg;  // 1 -> -mu
-        acc[h][m] = h == 0 ? 0u : (sgn ? 0u - kMu : kMu);
+        acc[h][m] = h == 0 ? 0u : (sgn ? 0u - mu : mu);
     }
 }
 
@@ -863,6 +919,55 @@ template <int THREADS>
 __device__ __forceinline__ void sample_extract(const uint32_t (&acc)[2][1024], uint32_t* o, int tid) {
     for (int m = tid; m < N; m += THREADS) o[m == 0 ? 0 : N - m] = m == 0 ? acc[0][0] : 0u - acc[0][m];
     if (tid == 0) o[N] = acc[1][0];
+}
+
+// Compound gate outputs.  The accumulator was rotated from the test vector
+// 1/16 by the phase of c1 + c2 (-1/4, 0, +1/4 for k = 0, 1, 2 true inputs);
+// the extractions of coefficients 3N/4 (E1) and N/4 (E2) then encrypt
+// (E1, E2) = (+,-), (+,+), (-,+) x 1/16 for k = 0, 1, 2.  A symmetric gate
+// with values g0, g1, g2 (+-1, units of 1/8) is the sample
+// (g1 - g2) E1 + (g1 - g0) E2 + (0, (g0 + g2)/16).  Extraction of
+// coefficient m: a'_j = a_(m-j) for j <= m, -a_(N+m-j) for j > m, b' = b_m.
+template <int THREADS>
+__device__ __forceinline__ void compound_extract(const uint32_t (&acc)[2][1024], uint32_t op0, uint32_t op1,
+                                                 uint32_t* o0, uint32_t* o1, int tid) {
+    constexpr int m1 = 3 * N / 4, m2 = N / 4;
+    const int32_t a0 = sym_value(op0, 0), a1 = sym_value(op0, 1), a2 = sym_value(op0, 2);
+    const int32_t b0 = sym_value(op1, 0), b1 = sym_value(op1, 1), b2 = sym_value(op1, 2);
+    const uint32_t x0 = (uint32_t)(a1 - a2), y0 = (uint32_t)(a1 - a0);
+    const uint32_t x1 = (uint32_t)(b1 - b2), y1 = (uint32_t)(b1 - b0);
+    for (int j = tid; j < N; j += THREADS) {
+        const uint32_t e1 = j <= m1 ? acc[0][m1 - j] : 0u - acc[0][N + m1 - j];
+        const uint32_t e2 = j <= m2 ? acc[0][m2 - j] : 0u - acc[0][N + m2 - j];
+        o0[j] = x0 * e1 + y0 * e2;
+        o1[j] = x1 * e1 + y1 * e2;
+    }
+    if (tid == 0) {
+        const uint32_t e1 = acc[1][m1], e2 = acc[1][m2];
+        o0[N] = x0 * e1 + y0 * e2 + (uint32_t)(a0 + a2) * (kMu >> 1);
+        o1[N] = x1 * e1 + y1 * e2 + (uint32_t)(b0 + b2) * (kMu >> 1);
+    }
+}
+
+// After the blind rotation: the extracted sample(s) of gate g into its
+// slot(s) of big; an invalid code gives all-zero samples (which key-switch
+// to the all-zero output) and is reported through io.err.
+template <int THREADS>
+__device__ __forceinline__ void gate_epilogue(const GateIO& io, uint32_t g, const uint32_t (&acc)[2][1024],
+                                              uint32_t* __restrict__ big, int tid) {
+    const GateMode m = gate_mode(io, g);
+    uint32_t* o = big + (size_t)(io.pair_slots ? 2 * g : g) * (N + 1);
+    if (!m.valid) {
+        const int words = (io.pair_slots ? 2 : 1) * (N + 1);
+        for (int j = tid; j < words; j += THREADS) o[j] = 0u;
+        if (tid == 0 && io.err)
+            __hip_atomic_store(io.err, 0x100u | (m.op0 & 0xFFu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return;
+    }
+    if (m.compound)
+        compound_extract<THREADS>(acc, m.op0, m.op1, o, o + N + 1, tid);
+    else
+        sample_extract<THREADS>(acc, o, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -890,7 +995,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
     auto& W = S.w[wave];
-    acc_init(W.acc, bbar, h, t, io.tv);
+    acc_init(W.acc, bbar, h, t, io.tv, gate_mu(io, g));
     wave_lds_sync();
 
     // Blind rotation.  abar_i = 0 would give D = 0 and leave ACC unchanged,
@@ -906,7 +1011,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
         }
     }
-    sample_extract<64>(W.acc, big + (size_t)g * (N + 1), lane);
+    gate_epilogue<64>(io, g, W.acc, big, lane);
 }
 
 // The same computation with two waves per gate (one gate per block), for
@@ -927,7 +1032,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv);
+    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv, gate_mu(io, g));
     __syncthreads();
 
     const uint64_t* bk = Arith<A>::bk(K);
@@ -1008,7 +1113,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
             }
         }
-        sample_extract<128>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
+        gate_epilogue<128>(io, g, S.acc, big, threadIdx.x);
         return;
     }
 #pragma unroll 1
@@ -1035,7 +1140,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
         }
     }
-    sample_extract<128>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
+    gate_epilogue<128>(io, g, S.acc, big, threadIdx.x);
 }
 
 // Four waves per gate (two-prime arithmetic), for the lowest latency: the
@@ -1052,7 +1157,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv);
+    if (wave == 0) acc_init(S.acc, bbar, h, t, io.tv, gate_mu(io, g));
     __syncthreads();
 
     const int32_t* twf = reinterpret_cast<const int32_t*>(S.twf);
@@ -1109,7 +1214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             for (int r = 0; r < 7; ++r) ab[r] = ab[r + 1];
         }
     }
-    sample_extract<256>(S.acc, big + (size_t)g * (N + 1), threadIdx.x);
+    gate_epilogue<256>(io, g, S.acc, big, threadIdx.x);
 }
 
 // Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
@@ -1121,6 +1226,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x * kWavesPerBlock + wave;
     if (g >= count) return;
+    uint32_t* o = ks_output(io, g);
+    if (!o) return;  // unused second slot of a single gate
     const uint32_t* src = big + (size_t)g * (N + 1);
     uint32_t acc[8];
 #pragma unroll
@@ -1144,7 +1251,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
             }
         }
     }
-    uint32_t* o = gate_output(io, g);
 #pragma unroll
     for (int e = 0; e < 8; ++e)
         if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
@@ -1167,6 +1273,8 @@ __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceK
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x;
     if (g >= count) return;  // uniform over the block
+    uint32_t* o = ks_output(io, g);
+    if (!o) return;  // unused second slot of a single gate (uniform over the block)
     const uint32_t* src = big + (size_t)g * (N + 1);
     uint32_t acc[8];
 #pragma unroll
@@ -1199,7 +1307,6 @@ __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceK
     for (int w = 1; w < kKsSplitWaves; ++w)
 #pragma unroll
         for (int e = 0; e < 8; ++e) acc[e] += part[w][8 * lane + e];
-    uint32_t* o = gate_output(io, g);
 #pragma unroll
     for (int e = 0; e < 8; ++e)
         if (8 * lane + e < NW) o[8 * lane + e] = acc[e];

@@ -126,9 +126,35 @@ static hipEvent_t take_event(fhe_ctx* ctx) {
     return e;
 }
 
-int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s) {
+int take_code_error(fhe_ctx* ctx) {
+    if (!ctx->err_host) return FHE_OK;
+    const uint32_t v = __atomic_exchange_n(ctx->err_host, 0u, __ATOMIC_ACQ_REL);
+    if (v == 0) return FHE_OK;
+    return set_error(FHE_EINVAL, "an earlier batch on this context held gate code %u, not valid for its call "
+                     "(its output is the all-zero sample)", v & 0xFFu);
+}
+
+int order_begin(fhe_ctx* ctx, hipStream_t s) {
+    if (!ctx->order_pending || ctx->order_stream == s) return FHE_OK;
+    hipError_t e = hipStreamWaitEvent(s, ctx->order, 0);
+    return e == hipSuccess ? FHE_OK : hip_fail(e, "stream ordering");
+}
+
+int order_end(fhe_ctx* ctx, hipStream_t s, int rc) {
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(ctx->order, s);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    ctx->order_stream = s;
+    ctx->order_pending = true;
+    return FHE_OK;
+}
+
+int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io_in, size_t count, hipStream_t s) {
     if (count == 0) return FHE_OK;
-    int rc = ctx_reserve_big(ctx, count);
+    dev::GateIO io = io_in;
+    io.err = ctx->err_dev;
+    const size_t samples = io.pair_slots ? 2 * count : count;
+    int rc = ctx_reserve_big(ctx, samples);
     if (rc) return rc;
     const dev::LaunchConfig cfg = launch_config_for(ctx, count);
     fhe_ctx::TimedLaunch tl{{nullptr, nullptr, nullptr}, count, cfg};
@@ -140,13 +166,23 @@ int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_
     hipError_t e = dev::launch_blind_rotate(ctx->keys, io, ctx->big, (uint32_t)count, cfg, s);
     if (e != hipSuccess) return hip_fail(e, "blind rotation launch");
     if (ctx->timing) (void)hipEventRecord(tl.ev[1], s);
-    e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)count, s);
+    e = dev::launch_key_switch(ctx->keys, io, ctx->big, (uint32_t)samples, s);
     if (e != hipSuccess) return hip_fail(e, "key switch launch");
     if (ctx->timing) {
         (void)hipEventRecord(tl.ev[2], s);
         ctx->timed.push_back(tl);
     }
     return FHE_OK;
+}
+
+// A batched entry point: earlier invalid codes reported, the call's work
+// ordered after the context's last call on another stream.
+int run_batch_call(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s) {
+    int rc = take_code_error(ctx);
+    if (rc) return rc;
+    rc = order_begin(ctx, s);
+    if (rc) return rc;
+    return order_end(ctx, s, run_gate_batch(ctx, io, count, s));
 }
 
 }  // namespace fhe
@@ -200,6 +236,12 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
     };
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) return fail(e, "stream");
+    if ((e = hipEventCreateWithFlags(&ctx->order, hipEventDisableTiming)) != hipSuccess) return fail(e, "event");
+    if ((e = hipHostMalloc((void**)&ctx->err_host, sizeof(uint32_t), hipHostMallocMapped)) != hipSuccess)
+        return fail(e, "error word");
+    *ctx->err_host = 0;
+    if ((e = hipHostGetDevicePointer((void**)&ctx->err_dev, ctx->err_host, 0)) != hipSuccess)
+        return fail(e, "error word");
     if ((e = hipMalloc((void**)&ctx->twf, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->twi, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->bkd, bkd_words * 8)) != hipSuccess) return fail(e, "bootstrapping key");
@@ -252,6 +294,8 @@ extern "C" void fhe_ctx_destroy(fhe_ctx* ctx) {
                         (void*)ctx->twi, (void*)ctx->big, (void*)ctx->bkq, (void*)ctx->twfq, (void*)ctx->twiq})
             if (p) (void)hipFree(p);
         if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        if (ctx->order) (void)hipEventDestroy(ctx->order);
+        if (ctx->err_host) (void)hipHostFree(ctx->err_host);
     }
     delete ctx;
 }
@@ -268,7 +312,7 @@ extern "C" int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const 
     io.in0 = in0;
     io.in1 = in1;
     io.out = out;
-    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+    return run_batch_call(ctx, io, count, (hipStream_t)stream);
 }
 
 extern "C" int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
@@ -284,7 +328,33 @@ extern "C" int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const
     io.in1 = in1;
     io.in2 = in2;
     io.out = out;
-    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+    return run_batch_call(ctx, io, count, (hipStream_t)stream);
+}
+
+extern "C" int fhe_bootstrap_compound_batch(fhe_ctx* ctx, const uint8_t* ops0, const uint8_t* ops1,
+                                            const uint32_t* in0, const uint32_t* in1, uint32_t* out0,
+                                            uint32_t* out1, size_t count, void* stream) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_bootstrap_compound_batch: null context");
+    if (count == 0) return FHE_OK;
+    if (!ops0 || !ops1 || !in0 || !in1 || !out0 || !out1)
+        return set_error(FHE_EINVAL, "fhe_bootstrap_compound_batch: null buffer");
+    if (count > (size_t)1 << 29)
+        return set_error(FHE_EINVAL, "fhe_bootstrap_compound_batch: count %zu too large", count);
+    DeviceGuard guard(ctx->device);
+    dev::GateIO io{};
+    io.ops = ops0;
+    io.ops1 = ops1;
+    io.in0 = in0;
+    io.in1 = in1;
+    io.out = out0;
+    io.out1 = out1;
+    io.pair_slots = 1;
+    return run_batch_call(ctx, io, count, (hipStream_t)stream);
+}
+
+extern "C" int fhe_ctx_check(fhe_ctx* ctx) {
+    if (!ctx) return set_error(FHE_EINVAL, "fhe_ctx_check: null context");
+    return take_code_error(ctx);
 }
 
 extern "C" int fhe_bootstrap_lut_batch(fhe_ctx* ctx, const uint32_t* tv, const uint32_t* in, uint32_t* out,
@@ -300,7 +370,7 @@ extern "C" int fhe_bootstrap_lut_batch(fhe_ctx* ctx, const uint32_t* tv, const u
     io.in1 = in;
     io.tv = tv;
     io.out = out;
-    return run_gate_batch(ctx, io, count, (hipStream_t)stream);
+    return run_batch_call(ctx, io, count, (hipStream_t)stream);
 }
 
 extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t* in0,
@@ -314,7 +384,7 @@ extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t
     io.in0 = in0;
     io.in1 = in1;
     io.out = out;
-    int rc = run_gate_batch(ctx, io, 1, (hipStream_t)stream);
+    int rc = run_batch_call(ctx, io, 1, (hipStream_t)stream);
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_bootstrap_gate_plain");

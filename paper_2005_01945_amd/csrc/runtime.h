@@ -46,6 +46,16 @@ struct fhe_ctx {
     };
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
+    // Calls on different streams share the scratch buffer and the circuit
+    // pools: each call records `order` on its stream, and a call on another
+    // stream first waits for it.
+    hipEvent_t order = nullptr;
+    hipStream_t order_stream = nullptr;
+    bool order_pending = false;
+    // Invalid gate codes met by a kernel (0 = none), pinned host memory the
+    // kernels write through err_dev.
+    uint32_t* err_host = nullptr;
+    uint32_t* err_dev = nullptr;
 };
 
 namespace fhe {
@@ -72,8 +82,19 @@ int ctx_reserve_big(fhe_ctx* ctx, size_t gates);
 int tune_bucket(size_t width);
 void tune_defaults(fhe_ctx* ctx);
 dev::LaunchConfig launch_config_for(const fhe_ctx* ctx, size_t width);
-// Enqueues blind rotation + key switching of `count` gates on stream s.
+// Enqueues blind rotation + key switching of `count` gates on stream s
+// (io.pair_slots: two extracted samples per gate).
 int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s);
+// Cross-stream ordering of a call's work (not used inside graph capture):
+// order_begin makes s wait for the context's last call on another stream,
+// order_end records the call's completion on s.
+int order_begin(fhe_ctx* ctx, hipStream_t s);
+int order_end(fhe_ctx* ctx, hipStream_t s, int rc);
+// FHE_EINVAL (and clears the word) when a kernel met an invalid gate code.
+int take_code_error(fhe_ctx* ctx);
+// run_gate_batch for an entry point: reports earlier invalid codes, orders
+// the work after the context's last call on another stream.
+int run_batch_call(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_t s);
 void destroy_circuit_cache(fhe_ctx* ctx);
 
 }  // namespace fhe

@@ -8,11 +8,17 @@
 //  2. gathers the next ASAP level of every running job into one descriptor
 //     batch and runs it as one blind-rotation + key-switching launch pair
 //     (jobs of different kinds and depths share the launch);
-//  3. retires jobs whose last level ran: copies their outputs to the caller's
-//     buffer, frees their pool samples, records the latency.
-// Jobs that arrive while a tick runs join the next one.  A gate's arithmetic
-// does not depend on the other gates of its launch, so a job's result is the
-// same alone and in any mix.
+//  3. copies the outputs of jobs whose last level ran to the caller's buffer
+//     and frees their pool samples.
+// Every tick goes to one stream, so a tick's gates see the outputs of the
+// previous ones and freed samples are reused only after their last reader.
+// A job's progress does not depend on device results, so the worker builds
+// and enqueues the next tick while earlier ones still run (up to kRing ticks
+// in flight, each with its own descriptor buffers and completion event): the
+// device is never idle between ticks.  A job is done when the event of its
+// last tick has completed.  Jobs that arrive meanwhile join the next tick.  A
+// gate's arithmetic does not depend on the other gates of its launch, so a
+// job's result is the same alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -108,7 +114,7 @@ struct Job {
     bool cancel = false;
     uint64_t base = 0;      // first pool slot
     uint32_t level = 0;     // next level to run
-    Clock::time_point submitted, finished;
+    Clock::time_point submitted, admitted, finished;
 };
 
 // First-fit allocator over pool slots.
@@ -156,16 +162,33 @@ class SlotAllocator {
 
 using namespace fhe;
 
+namespace fhe {
+namespace {
+// One tick in flight: its descriptors (device, and pinned staging the upload
+// reads from), the event recorded after its work, the jobs it finishes.
+struct Tick {
+    uint4* d_desc = nullptr;
+    uint4* h_desc = nullptr;
+    uint32_t* d_desc3 = nullptr;  // third inputs
+    uint32_t* h_desc3 = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    uint64_t gates = 0;
+    std::vector<Job*> finishing;
+};
+constexpr int kRing = 3;
+}  // namespace
+}  // namespace fhe
+
 struct fhe_server {
     fhe_ctx* ctx = nullptr;
     uint64_t capacity = 0;   // pool samples
     uint32_t* pool = nullptr;
     hipStream_t stream = nullptr;
-    uint4* d_desc = nullptr;
-    uint4* h_desc = nullptr;  // pinned staging
-    uint32_t* d_desc3 = nullptr;  // third inputs
-    uint32_t* h_desc3 = nullptr;
-    size_t desc_cap = 0;
+    Tick ring[kRing];
+    int next_tick = 0;
+    std::deque<int> inflight;  // ring indices in launch order
     std::unique_ptr<SlotAllocator> slots;
 
     std::mutex mu;
@@ -195,40 +218,94 @@ const ServeShape* shape_for(fhe_server* S, const fhe_job& j) {
     return &it->second;
 }
 
-int ensure_desc(fhe_server* S, size_t n) {
-    if (n <= S->desc_cap) return FHE_OK;
-    size_t cap = std::max<size_t>(n, 2 * S->desc_cap);
+void free_tick(Tick& T) {
+    if (T.d_desc) (void)hipFree(T.d_desc);
+    if (T.h_desc) (void)hipHostFree(T.h_desc);
+    if (T.d_desc3) (void)hipFree(T.d_desc3);
+    if (T.h_desc3) (void)hipHostFree(T.h_desc3);
+    T.d_desc = nullptr;
+    T.h_desc = nullptr;
+    T.d_desc3 = nullptr;
+    T.h_desc3 = nullptr;
+    T.cap = 0;
+}
+
+// Descriptor room for n gates in tick T (T is not in flight).
+int ensure_desc(Tick& T, size_t n) {
+    if (n <= T.cap) return FHE_OK;
+    size_t cap = std::max<size_t>(n, 2 * T.cap);
     cap = std::max<size_t>(cap, 4096);
-    if (S->d_desc) (void)hipFree(S->d_desc);
-    if (S->h_desc) (void)hipHostFree(S->h_desc);
-    if (S->d_desc3) (void)hipFree(S->d_desc3);
-    if (S->h_desc3) (void)hipHostFree(S->h_desc3);
-    S->d_desc = nullptr;
-    S->h_desc = nullptr;
-    S->d_desc3 = nullptr;
-    S->h_desc3 = nullptr;
-    S->desc_cap = 0;
-    hipError_t e = hipMalloc((void**)&S->d_desc, cap * sizeof(uint4));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_desc, cap * sizeof(uint4), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc((void**)&S->d_desc3, cap * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_desc3, cap * sizeof(uint32_t), hipHostMallocDefault);
+    free_tick(T);
+    hipError_t e = hipMalloc((void**)&T.d_desc, cap * sizeof(uint4));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&T.h_desc, cap * sizeof(uint4), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&T.d_desc3, cap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&T.h_desc3, cap * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "serving descriptors");
-    S->desc_cap = cap;
+    T.cap = cap;
     return FHE_OK;
 }
 
 uint32_t pool_wire(uint64_t slot) { return (3u << 30) | (uint32_t)slot; }
 
+// Marks the jobs of completed ticks done (blocking on the oldest tick when
+// `block`); returns a device error, if any.  Called without the lock.
+int reap(fhe_server* S, bool block) {
+    int rc = FHE_OK;
+    while (!S->inflight.empty()) {
+        Tick& T = S->ring[S->inflight.front()];
+        hipError_t e = block ? hipEventSynchronize(T.done) : hipEventQuery(T.done);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) rc = hip_fail(e, "serving tick");
+        block = false;
+        const Clock::time_point now = Clock::now();
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (Job* j : T.finishing) {
+            if (rc == FHE_OK) {
+                j->state = kDone;
+                j->finished = now;
+                S->jobs_done++;
+            } else {
+                j->state = kFailed;
+                j->error = rc;
+            }
+        }
+        S->gates_done += rc == FHE_OK ? T.gates : 0;
+        T.finishing.clear();
+        T.busy = false;
+        S->inflight.pop_front();
+        if (rc != FHE_OK) S->fatal = rc;
+        S->cv.notify_all();
+    }
+    return rc;
+}
+
+void fail_running(fhe_server* S, int rc) {
+    for (Job* j : S->running) {
+        j->state = kFailed;
+        j->error = rc;
+        S->slots->release(j->base, j->shape->slots);
+    }
+    S->running.clear();
+    S->fatal = rc;
+    S->cv.notify_all();
+}
+
 void worker_loop(fhe_server* S) {
     (void)hipSetDevice(S->ctx->device);
     const size_t W = kLweW;
-    std::vector<Job*> tick;
     for (;;) {
+        if (reap(S, false) != FHE_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            fail_running(S, S->fatal);
+        }
+        Tick* T = nullptr;
         size_t ngates = 0;
         bool three = false;
+        int rc = FHE_OK;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // retire cancelled running jobs
+            // retire cancelled running jobs (ticks already enqueued may still
+            // write their samples; anything reusing them is enqueued later)
             for (auto it = S->running.begin(); it != S->running.end();) {
                 Job* j = *it;
                 if (j->cancel) {
@@ -253,6 +330,7 @@ void worker_loop(fhe_server* S) {
                 if (!S->slots->alloc(j->shape->slots, &at)) break;
                 j->base = at;
                 j->state = kRunning;
+                j->admitted = Clock::now();
                 const size_t na = j->shape->na, nb = j->shape->nb;
                 hipError_t e = hipMemcpyAsync(S->pool + at * W, j->spec.in0, na * W * 4, hipMemcpyDeviceToDevice, S->stream);
                 if (e == hipSuccess)
@@ -269,73 +347,87 @@ void worker_loop(fhe_server* S) {
                 S->running.push_back(j);
             }
             if (S->running.empty()) {
-                if (S->stop) return;
-                S->cv.wait_for(lk, std::chrono::milliseconds(2));
+                if (S->inflight.empty()) {
+                    if (S->stop) return;
+                    S->cv.wait_for(lk, std::chrono::milliseconds(2));
+                    continue;
+                }
+                lk.unlock();
+                reap(S, true);  // nothing new to launch: wait for the oldest tick
                 continue;
             }
-            tick = S->running;
-            for (Job* j : tick) ngates += j->shape->levels[j->level].size();
-            if (ensure_desc(S, ngates) != FHE_OK) {
-                for (Job* j : tick) { j->state = kFailed; j->error = FHE_ENOMEM; S->slots->release(j->base, j->shape->slots); }
-                S->running.clear();
-                S->cv.notify_all();
+            T = &S->ring[S->next_tick];
+            if (T->busy) {  // kRing ticks in flight: wait for the oldest
+                lk.unlock();
+                reap(S, true);
+                continue;
+            }
+            for (Job* j : S->running) ngates += j->shape->levels[j->level].size();
+            rc = ensure_desc(*T, ngates);
+            if (rc != FHE_OK) {
+                fail_running(S, rc);
                 continue;
             }
             size_t k = 0;
-            three = false;
-            for (Job* j : tick) {
+            T->finishing.clear();
+            for (auto it = S->running.begin(); it != S->running.end();) {
+                Job* j = *it;
                 const ServeShape& sh = *j->shape;
                 three |= sh.three;
                 for (uint32_t g : sh.levels[j->level]) {
-                    S->h_desc3[k] = sh.in2[g] != kNoWire ? pool_wire(j->base + sh.in2[g]) : 0u;
-                    S->h_desc[k++] = make_uint4(sh.op[g], pool_wire(j->base + sh.in0[g]),
+                    T->h_desc3[k] = sh.in2[g] != kNoWire ? pool_wire(j->base + sh.in2[g]) : 0u;
+                    T->h_desc[k++] = make_uint4(sh.op[g], pool_wire(j->base + sh.in0[g]),
                                                 pool_wire(j->base + sh.in1[g]), pool_wire(j->base + sh.out[g]));
                 }
+                if (++j->level == sh.levels.size()) {
+                    // last level: its output copy is enqueued with this tick,
+                    // before anything that could reuse its samples
+                    T->finishing.push_back(j);
+                    S->slots->release(j->base, sh.slots);
+                    it = S->running.erase(it);
+                } else {
+                    ++it;
+                }
             }
+            S->launches++;
         }
-        // one launch pair for the whole frontier
-        hipError_t e = hipMemcpyAsync(S->d_desc, S->h_desc, ngates * sizeof(uint4), hipMemcpyHostToDevice, S->stream);
+        // one launch pair for the whole frontier, then the finished jobs' outputs
+        hipError_t e = hipMemcpyAsync(T->d_desc, T->h_desc, ngates * sizeof(uint4), hipMemcpyHostToDevice, S->stream);
         if (e == hipSuccess && three)
-            e = hipMemcpyAsync(S->d_desc3, S->h_desc3, ngates * sizeof(uint32_t), hipMemcpyHostToDevice, S->stream);
-        int rc = e == hipSuccess ? FHE_OK : hip_fail(e, "serving descriptor upload");
+            e = hipMemcpyAsync(T->d_desc3, T->h_desc3, ngates * sizeof(uint32_t), hipMemcpyHostToDevice, S->stream);
+        rc = e == hipSuccess ? FHE_OK : hip_fail(e, "serving descriptor upload");
         if (rc == FHE_OK) {
             dev::GateIO io{};
-            io.desc = S->d_desc;
-            io.desc3 = three ? S->d_desc3 : nullptr;
+            io.desc = T->d_desc;
+            io.desc3 = three ? T->d_desc3 : nullptr;
             io.region[3] = S->pool;
             rc = run_gate_batch(S->ctx, io, ngates, S->stream);
         }
-        for (Job* j : tick) {
-            if (rc != FHE_OK || j->level + 1 != j->shape->levels.size()) continue;
+        for (Job* j : T->finishing) {
+            if (rc != FHE_OK) break;
             const ServeShape& sh = *j->shape;
             e = hipMemcpyAsync(j->spec.out, S->pool + (j->base + sh.na + sh.nb) * W, (size_t)sh.nout * W * 4,
                                hipMemcpyDeviceToDevice, S->stream);
             if (e != hipSuccess) rc = hip_fail(e, "serving output copy");
         }
         if (rc == FHE_OK) {
-            e = hipStreamSynchronize(S->stream);
-            if (e != hipSuccess) rc = hip_fail(e, "serving tick");
+            e = hipEventRecord(T->done, S->stream);
+            if (e != hipSuccess) rc = hip_fail(e, "serving tick event");
         }
-        const Clock::time_point now = Clock::now();
         std::lock_guard<std::mutex> lk(S->mu);
-        S->launches++;
-        S->gates_done += rc == FHE_OK ? ngates : 0;
-        for (Job* j : tick) {
-            if (rc != FHE_OK) {
+        if (rc != FHE_OK) {
+            for (Job* j : T->finishing) {
                 j->state = kFailed;
                 j->error = rc;
-            } else if (++j->level < j->shape->levels.size()) {
-                continue;
-            } else {
-                j->state = kDone;
-                j->finished = now;
-                S->jobs_done++;
             }
-            S->slots->release(j->base, j->shape->slots);
-            S->running.erase(std::find(S->running.begin(), S->running.end(), j));
+            T->finishing.clear();
+            fail_running(S, rc);
+            continue;
         }
-        if (rc != FHE_OK) S->fatal = rc;
-        S->cv.notify_all();
+        T->gates = ngates;
+        T->busy = true;
+        S->inflight.push_back(S->next_tick);
+        S->next_tick = (S->next_tick + 1) % kRing;
     }
 }
 
@@ -352,11 +444,18 @@ extern "C" int fhe_serve_create(fhe_ctx* ctx, size_t hbm_budget_bytes, fhe_serve
     if (!S) return set_error(FHE_ENOMEM, "fhe_serve_create: out of host memory");
     S->ctx = ctx;
     S->capacity = capacity;
-    hipError_t e = hipMalloc((void**)&S->pool, capacity * kLweW * 4);
+    // work of earlier calls on the context (any stream) completes first
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMalloc((void**)&S->pool, capacity * kLweW * 4);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    for (Tick& T : S->ring)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&T.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "fhe_serve_create");
         if (S->pool) (void)hipFree(S->pool);
+        if (S->stream) (void)hipStreamDestroy(S->stream);
+        for (Tick& T : S->ring)
+            if (T.done) (void)hipEventDestroy(T.done);
         delete S;
         return rc;
     }
@@ -414,6 +513,21 @@ extern "C" int fhe_serve_poll(fhe_server* S, uint64_t ticket, int* state, double
     return FHE_OK;
 }
 
+extern "C" int fhe_serve_job_times(fhe_server* S, uint64_t ticket, double* queue_ms, double* service_ms) {
+    if (!S) return set_error(FHE_EINVAL, "fhe_serve_job_times: null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(ticket);
+    if (it == S->jobs.end())
+        return set_error(FHE_EINVAL, "fhe_serve_job_times: unknown ticket %llu", (unsigned long long)ticket);
+    const Job* J = it->second;
+    if (J->state != kDone)
+        return set_error(FHE_EINVAL, "fhe_serve_job_times: job %llu is not done", (unsigned long long)ticket);
+    using ms = std::chrono::duration<double, std::milli>;
+    if (queue_ms) *queue_ms = ms(J->admitted - J->submitted).count();
+    if (service_ms) *service_ms = ms(J->finished - J->admitted).count();
+    return FHE_OK;
+}
+
 extern "C" int fhe_serve_wait(fhe_server* S, uint64_t ticket, double timeout_s) {
     if (!S) return set_error(FHE_EINVAL, "fhe_serve_wait: null server");
     std::unique_lock<std::mutex> lk(S->mu);
@@ -466,10 +580,10 @@ extern "C" void fhe_serve_destroy(fhe_server* S) {
         DeviceGuard guard(S->ctx->device);
         (void)hipStreamSynchronize(S->stream);
         if (S->pool) (void)hipFree(S->pool);
-        if (S->d_desc) (void)hipFree(S->d_desc);
-        if (S->h_desc) (void)hipHostFree(S->h_desc);
-        if (S->d_desc3) (void)hipFree(S->d_desc3);
-        if (S->h_desc3) (void)hipHostFree(S->h_desc3);
+        for (Tick& T : S->ring) {
+            free_tick(T);
+            if (T.done) (void)hipEventDestroy(T.done);
+        }
         if (S->stream) (void)hipStreamDestroy(S->stream);
     }
     for (auto& kv : S->jobs) delete kv.second;

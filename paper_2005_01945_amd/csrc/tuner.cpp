@@ -99,6 +99,9 @@ extern "C" int fhe_ctx_autotune(fhe_ctx* ctx, uint32_t max_width, uint32_t reps)
     const int top = tune_bucket(max_width);
     const size_t widest = (size_t)1 << top;
     DeviceGuard guard(ctx->device);
+    // work of earlier calls on any stream may still use the scratch buffer
+    hipError_t e0 = hipDeviceSynchronize();
+    if (e0 != hipSuccess) return hip_fail(e0, "fhe_ctx_autotune");
     int rc = ctx_reserve_big(ctx, widest);
     if (rc) return rc;
     // Synthetic batch: all-zero input samples (any words are valid input).

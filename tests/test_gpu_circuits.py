@@ -8,6 +8,7 @@ import pytest
 import oracle
 import paper_2005_01945_amd as F
 import workloads
+from sampled import check_sampled_levels, evaluate_cone, pure_cone
 
 pytestmark = pytest.mark.gpu
 
@@ -24,12 +25,16 @@ def env():
     return sk, F.Context(ck, 0), oracle.Keys(0)
 
 
-def gpu_binary(ctx, fn, ca, cb, count, width):
+def gpu_binary(ctx, fn, ca, cb, count, width, keep=None):
+    """Runs fn on device copies of ca, cb; with keep = [] the device buffers
+    (A, B, R) are appended to it for later wire reads."""
     import torch
     dA, dB = F.to_device(ca), F.to_device(cb)
     dR = torch.empty_like(dA)
     fn(ctx, dA, dB, dR, count, width)
     torch.cuda.synchronize()
+    if keep is not None:
+        keep.extend([dA, dB, dR])
     return F.to_host(dR)
 
 
@@ -108,18 +113,22 @@ def test_matvec_bit_exact(env, rows, cols, width):
 def test_add16_full_size(env):
     """1024 pairs of uniform uint16 in one level-scheduled run (the benchmark's
     launch configuration and balanced schedule): every sum decrypts correctly,
-    pairs 0-7 and the last pair are bit-exact end to end (666 gates)."""
+    pairs 0-7 and the last pair are bit-exact end to end (666 gates), 64
+    sampled gates of every level are bit-exact teacher-forced."""
     sk, ctx, K = env
     wl = workloads.AddWorkload()
     a, b = wl.operands()
     ca = sk.encrypt_uint(a, wl.width, nonce=0)
     cb = sk.encrypt_uint(b, wl.width, nonce=1 << 40)
     log("add16 x 1024 pairs")
-    got = gpu_binary(ctx, F.fhe_add, ca, cb, wl.count, wl.width)
+    dev = []
+    got = gpu_binary(ctx, F.fhe_add, ca, cb, wl.count, wl.width, keep=dev)
     np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (a + b) % (1 << wl.width))
     pick = list(range(8)) + [wl.count - 1]
     log("oracle: pairs 0-7 and 1023 end to end")
     np.testing.assert_array_equal(got[pick], K.add(ca[pick], cb[pick], wl.width))
+    # 64 gates of every level (first, last and random between), teacher-forced
+    check_sampled_levels(ctx, K, "add", wl.width, *dev, count=wl.count, seed=2, log=log)
 
 
 @pytest.mark.parametrize("width,count", [(1, 1), (5, 2), (8, 3)])
@@ -235,20 +244,23 @@ def test_matmul16_4x4_decrypts(env):
     np.testing.assert_array_equal(got, (A.astype(object) @ B.astype(object)) % (1 << 16))
 
 
-def test_mul32_full_size_decrypts(env):
+def test_mul32_full_size(env):
     """256 pairs of uniform uint32 (722,944 gates, 120 levels): every low-32-bit
-    product decrypts correctly, pair 0 is bit-exact end to end (2,824 gates)."""
+    product decrypts correctly, pair 0 is bit-exact end to end (2,824 gates),
+    64 sampled gates of every level are bit-exact teacher-forced."""
     sk, ctx, K = env
     wl = workloads.MulWorkload()
     a, b = wl.operands()
     ca = sk.encrypt_uint(a, wl.width, nonce=0)
     cb = sk.encrypt_uint(b, wl.width, nonce=1 << 40)
     log("mul32 x 256 pairs")
-    got = gpu_binary(ctx, F.fhe_mul, ca, cb, wl.count, wl.width)
+    dev = []
+    got = gpu_binary(ctx, F.fhe_mul, ca, cb, wl.count, wl.width, keep=dev)
     want = (a.astype(object) * b.astype(object)) % (1 << 32)
     np.testing.assert_array_equal(sk.decrypt_uint(got, 32).astype(object), want)
     log("oracle: mul32 pair 0 end to end (2,824 gates)")
     np.testing.assert_array_equal(got[0], K.mul(ca[:1], cb[:1], wl.width)[0])
+    check_sampled_levels(ctx, K, "mul", wl.width, *dev, count=wl.count, seed=3, log=log)
 
 
 def test_mul8_in_wide_batch_bit_exact(env):
@@ -280,11 +292,12 @@ def test_matvec8_serving_size_decrypts(env):
     np.testing.assert_array_equal(sk.decrypt_uint(F.to_host(dy), 8), (M @ x) % 256)
 
 
-def test_matvec64_full_size_decrypts(env):
+def test_matvec64_full_size(env):
     """The 64x64 16-bit matrix-vector product with entries in [0, 256)
     (2,952,576 gates in 68 levels, all 4096 products batched per level):
     every output decrypts to M x mod 2^16 (row sums exceed 2^16, so the
-    wraparound is exercised)."""
+    wraparound is exercised), 64 sampled gates of every level are bit-exact
+    teacher-forced, and product (0, 0) is bit-exact end to end (648 gates)."""
     import torch
     sk, ctx, K = env
     wl = workloads.MatvecWorkload()
@@ -294,10 +307,35 @@ def test_matvec64_full_size_decrypts(env):
     cx = sk.encrypt_uint(x, wl.width, nonce=1 << 40)
     dy = torch.empty((wl.rows, wl.width, F.WORDS), dtype=torch.int32, device="cuda")
     log("matvec 64x64 16-bit (2.95 M gates)")
-    F.fhe_matvec(ctx, F.to_device(cm), F.to_device(cx), dy, wl.rows, wl.cols, wl.width)
+    dM, dx = F.to_device(cm), F.to_device(cx)
+    F.fhe_matvec(ctx, dM, dx, dy, wl.rows, wl.cols, wl.width)
     torch.cuda.synchronize()
     got = F.to_host(dy)
     np.testing.assert_array_equal(sk.decrypt_uint(got, wl.width), (M @ x) % (1 << wl.width))
+    w, shape = wl.width, dict(rows=wl.rows, cols=wl.cols)
+    check_sampled_levels(ctx, K, "matvec", w, dM, dx, dy, seed=4, log=log, **shape)
+
+    # Product (0, 0) end to end: the gates that read only M[0][0] and x[0]
+    # (and each other) are that product's multiplier; the oracle evaluates
+    # them from the two input integers and every one of their words must
+    # equal the GPU's, and the oracle's own 16-bit multiplier (its own
+    # wiring) must produce the cone's 16 output words.
+    gates, off = F.fhe_debug_plan(ctx, "matvec", w, 1, **shape)
+    cmf, cxf = cm.reshape(-1, F.WORDS), cx.reshape(-1, F.WORDS)
+    inputs = {int(k): cmf[k] for k in range(w)}  # region A (M), samples 0..w-1 = M[0][0]
+    inputs.update({(1 << 30) | k: cxf[k] for k in range(w)})  # region B (x), x[0]
+    cone = pure_cone(gates, inputs.keys())
+    assert len(cone) == F.fhe_circuit_shape("mul", w)[0] == 648
+    log(f"oracle: product (0,0), {len(cone)} gates end to end")
+    val = evaluate_cone(K, gates, off, cone, inputs)
+    outs = gates[cone, 3]
+    gpu = F.fhe_debug_read_wires(ctx, "matvec", w, dM, dx, dy, outs, 1, **shape)
+    np.testing.assert_array_equal(gpu, np.stack([val[int(o)] for o in outs]))
+    inner = set(int(v) for v in gates[cone][:, 1:3].reshape(-1))
+    last = [i for i, o in enumerate(outs) if int(o) not in inner]  # no gate of the cone reads them
+    own = K.mul(cmf[:w].reshape(1, w, -1), cxf[:w].reshape(1, w, -1), w)[0]
+    assert len(last) == w
+    assert {r.tobytes() for r in own} == {gpu[i].tobytes() for i in last}
 
 
 def test_custom_circuit_bit_exact(env):

@@ -199,6 +199,30 @@ def test_wide_ragged_batch_sampled_bit_exact(env, n):
     np.testing.assert_array_equal(got[pick], K.bootstrap(ops[pick], c0[pick], c1[pick], threads=5))
 
 
+def test_widest_matvec_level_as_one_batch(env):
+    """One batch as wide as the widest level of the 64x64 16-bit matrix-vector
+    product (557,056 gates: about 70k blind-rotation workgroups and 557k
+    key-switching workgroups in one launch pair): every gate decrypts to its
+    truth table, and 16 sampled gates, the first and the last among them,
+    are bit-exact against the oracle."""
+    sk, ctx, K = env
+    n = F.fhe_circuit_shape("matvec", 16, 64, 64)[2]
+    assert n == 557_056
+    ops = workloads.gate_ops(510, n)
+    A = workloads.bits(511, n).astype(int)
+    B = workloads.bits(512, n).astype(int)
+    c0 = sk.encrypt_bits(A, nonce=1 << 45)
+    c1 = sk.encrypt_bits(B, nonce=(1 << 45) + n)
+    log(f"widest matvec level as one batch: {n} gates")
+    got = run_batch(ctx, ops, c0, c1)
+    table = np.array([A & B, 1 - (A & B), A | B, 1 - (A | B), A ^ B, 1 - (A ^ B),
+                      (1 - A) & B, A & (1 - B), (1 - A) | B, A | (1 - B)])
+    np.testing.assert_array_equal(sk.decrypt_bits(got), table[ops.astype(int), np.arange(n)])
+    pick = np.unique(np.concatenate([[0, 1, n - 2, n - 1], np.linspace(0, n - 1, 12).astype(np.int64)]))
+    log(f"oracle: {len(pick)} sampled gates")
+    np.testing.assert_array_equal(got[pick], K.bootstrap(ops[pick], c0[pick], c1[pick]))
+
+
 def test_three_input_gates_bit_exact(env):
     """MAJ and XOR3 on all eight input combinations, and two-input codes
     through the three-input entry point (third input ignored), against the

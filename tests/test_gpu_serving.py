@@ -1,6 +1,7 @@
 """Serving (continuous batching): every job's output is byte-identical alone
-and in a mix, decrypts to the plaintext result, and admission respects the
-HBM budget (queueing when full, refusing what can never fit)."""
+and in a mix, equal to the same job run through its own entry point and to
+the oracle, decrypts to the plaintext result, and admission respects the HBM
+budget (queueing when full, refusing what can never fit)."""
 import numpy as np
 import pytest
 
@@ -85,6 +86,8 @@ def test_alone_equals_mix_and_decrypts(env):
             F.fhe_serve_wait(srv, t, 300)
             st, lat = F.fhe_serve_poll(srv, t)
             assert st == F.FHE_JOB_DONE and lat > 0
+            q, v = F.fhe_serve_job_times(srv, t)
+            assert q >= 0 and v > 0 and abs(q + v - lat) < 1e-6 * max(lat, 1.0) + 1e-3
             alone.append(F.to_host(out))
         outs = [torch.zeros(j["shape"], dtype=torch.int32, device="cuda") for j in jobs]
         log("serving: all jobs in one mix")
@@ -101,9 +104,48 @@ def test_alone_equals_mix_and_decrypts(env):
         assert stats["jobs_done"] == 2 * len(jobs) and stats["pool_bytes_in_use"] == 0
     finally:
         srv.close()
-    # a served gate is bit-exact with the oracle
+    # The server runs its own slot layout and level order; a gate's words do
+    # not depend on either, so every served job must give the words of its
+    # direct entry point and of the oracle.
     K = oracle.Keys(0)
-    np.testing.assert_array_equal(alone[0], K.bootstrap([jobs[0]["op"]], jobs[0]["a"], jobs[0]["b"]))
+    for j, a in zip(jobs, alone):
+        log(f"served job kind {j['kind']} width {j['width']}: direct entry point and oracle")
+        np.testing.assert_array_equal(a, direct_run(ctx, j))
+        np.testing.assert_array_equal(a.reshape(-1, F.WORDS), oracle_run(K, j).reshape(-1, F.WORDS))
+
+
+def direct_run(ctx, j):
+    """The job through its own entry point (no server)."""
+    import torch
+    out = torch.zeros(j["shape"], dtype=torch.int32, device="cuda")
+    k, w, da, db = j["kind"], j["width"], j["da"], j["db"]
+    if k == F.FHE_JOB_GATE:
+        ops = torch.tensor([j["op"]], dtype=torch.uint8, device="cuda")
+        F.fhe_bootstrap_gate_batch(ctx, ops, da, db, out, 1)
+    elif k == F.FHE_JOB_MATVEC:
+        F.fhe_matvec(ctx, da, db, out, j["rows"], j["cols"], w)
+    elif k == F.FHE_JOB_MATMUL:
+        F.fhe_matmul(ctx, da, db, out, j["rows"], w)
+    else:
+        fn = {F.FHE_JOB_ADD: F.fhe_add, F.FHE_JOB_MUL: F.fhe_mul, F.FHE_JOB_MUL_TREE: F.fhe_mul_tree,
+              F.FHE_JOB_ADD_FA: F.fhe_add_fa, F.FHE_JOB_ADD_NUMBERWISE: F.fhe_add_numberwise,
+              F.FHE_JOB_KARATSUBA: F.fhe_mul_karatsuba}[k]
+        fn(ctx, da, db, out, 1, w)
+    torch.cuda.synchronize()
+    return F.to_host(out)
+
+
+def oracle_run(K, j):
+    k, w, a, b = j["kind"], j["width"], j["a"], j["b"]
+    if k == F.FHE_JOB_GATE:
+        return K.bootstrap([j["op"]], a, b)
+    if k == F.FHE_JOB_MATVEC:
+        return K.matvec(a, b, j["rows"], j["cols"], w)
+    if k == F.FHE_JOB_MATMUL:
+        return K.matmul(a, b, j["rows"], w)
+    fn = {F.FHE_JOB_ADD: K.add, F.FHE_JOB_MUL: K.mul, F.FHE_JOB_MUL_TREE: K.mul_tree, F.FHE_JOB_ADD_FA: K.add_fa,
+          F.FHE_JOB_ADD_NUMBERWISE: K.add_numberwise, F.FHE_JOB_KARATSUBA: K.karatsuba}[k]
+    return fn(a.reshape(1, w, -1), b.reshape(1, w, -1), w)
 
 
 def test_small_budget_queues_and_refuses(env):

@@ -114,6 +114,8 @@ def test_argument_errors():
     assert b"null context" in L.fhe_last_error()
     assert L.fhe_debug_cmux(0, 0, None, 0, None) == F.FHE_EINVAL
     assert L.fhe_debug_cmux(0, 2, None, 0, None) == F.FHE_EINVAL
+    assert L.fhe_debug_plan(None, 0, 16, 0, 0, 1, None, 0, None, 0, None, None) == F.FHE_EINVAL
+    assert L.fhe_debug_read_wires(None, 0, 16, 0, 0, 1, None, None, None, None, 0, None) == F.FHE_EINVAL
 
 
 def test_circuit_shapes_match_oracle_gate_counts():
@@ -130,6 +132,10 @@ def test_circuit_shapes_match_oracle_gate_counts():
     for w in (1, 2, 5, 16, 32):
         assert F.fhe_circuit_shape("add_fa", w)[0] == oracle.circuit_gate_count("add_fa", w)
     assert F.fhe_circuit_shape("add_fa", 16) == (31, 16, 2)
+    for w in (1, 2, 3, 16, 32):  # a compound node counts once
+        assert F.fhe_circuit_shape("add_compound", w)[0] == oracle.circuit_gate_count("add_compound", w) == \
+            (1 if w == 1 else 3 * w - 3)
+    assert F.fhe_circuit_shape("add_compound", 16)[1] == F.fhe_circuit_shape("add", 16)[1]
     assert F.fhe_circuit_shape("matvec", 16, 64, 64)[0] == oracle.circuit_gate_count("matvec", 16, 64, 64)
     assert F.fhe_circuit_shape("matvec", 3, 5, 7)[0] == oracle.circuit_gate_count("matvec", 3, 5, 7)
     # gates, ASAP depth, widest level of the paper-sized circuits
