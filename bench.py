@@ -365,6 +365,8 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=50)
     ap.add_argument("--mul-samples", type=int, default=50)
     ap.add_argument("--circuit-samples", type=int, default=5)
+    ap.add_argument("--compound-samples", type=int, default=10,
+                    help="samples of the compound-gate against two-single-gates comparison (0: skip)")
     ap.add_argument("--cpu-sample-gates", type=int, default=768)
     ap.add_argument("--cpu-single-gates", type=int, default=48)
     ap.add_argument("--tune-max-width", type=int, default=4096,
@@ -494,6 +496,41 @@ def main():
         if not add_cfg["verify"]():
             raise SystemExit("bench: Goldilocks-path results differ from plaintext arithmetic")
         log(f"Goldilocks NTT: {goldilocks}")
+
+    # compound gates (Sec. V-A-3, Fig. 5c): the XOR and the AND of the same
+    # inputs from one blind rotation, against the two single gates in one batch
+    compound = None
+    if args.compound_samples > 0:
+        compound = {}
+        for n in (1, 32, 2048):
+            a_bits, b_bits = workloads.bits(80, n), workloads.bits(81, n)
+            c0 = sk.encrypt_bits(a_bits, nonce=(1 << 51) + 10 * n)
+            c1 = sk.encrypt_bits(b_bits, nonce=(1 << 51) + 10 * n + 4096)
+            d0, d1 = F.to_device(c0), F.to_device(c1)
+            d00, d11 = torch.cat([d0, d0]), torch.cat([d1, d1])
+            ox = torch.full((n,), F.XOR, dtype=torch.uint8, device="cuda")
+            oa = torch.full((n,), F.AND, dtype=torch.uint8, device="cuda")
+            oxa = torch.cat([ox, oa])
+            o0, o1, o2 = torch.empty_like(d0), torch.empty_like(d0), torch.empty_like(d00)
+            single = latency(lambda: F.fhe_bootstrap_gate_batch(ctx, oxa, d00, d11, o2, 2 * n, stream),
+                             args.compound_samples)
+            comp = latency(lambda: F.fhe_bootstrap_compound_batch(ctx, ox, oa, d0, d1, o0, o1, n, stream),
+                           args.compound_samples)
+            assert (sk.decrypt_bits(F.to_host(o0)) == (a_bits ^ b_bits)).all()
+            assert (sk.decrypt_bits(F.to_host(o1)) == (a_bits & b_bits)).all()
+            assert (sk.decrypt_bits(F.to_host(o2)) == np.concatenate([a_bits ^ b_bits, a_bits & b_bits])).all()
+            compound[f"{n}_pairs"] = {"compound_ms": comp["p50_ms"], "two_single_gates_ms": single["p50_ms"],
+                                      "single_over_compound": round(single["p50_ms"] / comp["p50_ms"], 2)}
+        wl = workloads.AddWorkload()
+        aA, aB, aR = add_cfg["dA"], add_cfg["dB"], add_cfg["dR"]
+        ca16 = latency(lambda: F.fhe_add_compound(ctx, aA, aB, aR, wl.count, wl.width, stream), 2)
+        assert add_cfg["verify"]()
+        rot = F.fhe_circuit_shape("add_compound", wl.width)[0] * wl.count
+        add_ms = legs["add16"]["ms_per_step"] if "add16" in legs else ms_per_step if args.config == "add16" else None
+        compound["add16_x1024"] = {"compound_ms": ca16["p50_ms"], "rotations": rot,
+                                   "two_input_gates_ms": add_ms,
+                                   "two_input_gates": F.fhe_circuit_shape("add", wl.width)[0] * wl.count}
+        log(f"compound gates: {compound}")
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
@@ -629,7 +666,7 @@ def main():
         "config": main_cfg["workload"],
         "plain": plain, "mul32_latency": mul, "mul32_tree_latency": mul_tree,
         "mul32_karatsuba_latency": mul_kara, "batched_legs": legs, "circuit_latency": circuits,
-        "goldilocks_ntt": goldilocks, "with_host_transfers": end_to_end,
+        "goldilocks_ntt": goldilocks, "compound_gates": compound, "with_host_transfers": end_to_end,
         "serving": serving,
         "phase_ms_per_step": res["phase_ms_per_step"],
         "key_switch_roofline": res["key_switch_roofline"],

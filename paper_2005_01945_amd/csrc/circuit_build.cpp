@@ -385,6 +385,56 @@ static double level_cost(uint64_t gates, uint64_t round) {
     return (double)((gates + round - 1) / round);
 }
 
+// List scheduling against the launch rounds: level by level, the ready gates
+// that must run now (their ALAP level) fix the number of rounds the level
+// takes, and the room left in its last round goes to the most urgent other
+// ready gates (smallest ALAP level first).  A level whose urgent gates fill
+// less than half a round runs on a narrower launch shape and is filled up to
+// one round only when `fill_narrow`.  Gates become ready one level after
+// their last input; the depth stays the critical path.
+static std::vector<uint32_t> list_schedule(const Circuit& c, const std::vector<uint32_t>& alap,
+                                           const std::vector<std::vector<uint32_t>>& cons, uint32_t depth,
+                                           size_t count, uint64_t round, bool fill_narrow) {
+    const size_t ng = c.gates.size();
+    const uint32_t base = c.na + c.nb;
+    std::vector<uint32_t> lev(ng, 0), pend(ng, 0);
+    for (size_t k = 0; k < ng; ++k) {
+        const Gate& g = c.gates[k];
+        for (uint32_t w : {g.in0, g.in1, g.in2})
+            if (w != kNoWire && w >= base) pend[k]++;
+    }
+    // ready gates by ALAP level; head[a] = first not yet taken in bucket a
+    std::vector<std::vector<uint32_t>> bucket(depth + 2);
+    std::vector<size_t> head(depth + 2, 0);
+    for (size_t k = 0; k < ng; ++k)
+        if (pend[k] == 0) bucket[alap[k]].push_back((uint32_t)k);
+    std::vector<uint32_t> fresh;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        fresh.clear();
+        auto take = [&](uint32_t k) {
+            lev[k] = L;
+            for (uint32_t q : cons[k])
+                if (--pend[q] == 0) fresh.push_back(q);
+        };
+        const uint64_t urgent = bucket[L].size() - head[L];
+        const uint64_t g = urgent * count;
+        uint64_t cap = urgent;  // gates per instance this level may take
+        if (2 * g > round || (fill_narrow && g > 0)) {
+            const uint64_t rounds = std::max<uint64_t>(1, (g + round - 1) / round);
+            cap = std::max<uint64_t>(urgent, rounds * round / count);
+        }
+        while (head[L] < bucket[L].size()) take(bucket[L][head[L]++]);
+        uint64_t room = cap - urgent;
+        for (uint32_t a = L + 1; a <= depth && room > 0; ++a)
+            while (room > 0 && head[a] < bucket[a].size()) {
+                take(bucket[a][head[a]++]);
+                room--;
+            }
+        for (uint32_t q : fresh) bucket[alap[q]].push_back(q);
+    }
+    return lev;
+}
+
 // Level balancing: ASAP levels put every gate whose inputs are ready at the
 // earliest level (e.g. all partial products and operand XORs/ANDs at level
 // 1), leaving the levels along the critical path narrow.  A gate with slack
@@ -398,6 +448,7 @@ static double level_cost(uint64_t gates, uint64_t round) {
 // computed are too.
 std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_t>& asap, uint32_t depth,
                                             size_t count, uint64_t round) {
+    if (c.has_compound()) return asap;  // compound nodes keep their ASAP levels (moved only as pairs)
     const size_t ng = c.gates.size();
     const uint32_t base = c.na + c.nb;
     std::vector<std::vector<uint32_t>> cons(ng);
@@ -416,7 +467,6 @@ std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_
     std::vector<uint32_t> lev(asap);
     std::vector<uint64_t> width(depth + 1, 0);
     for (uint32_t l : lev) width[l]++;
-    const std::vector<uint64_t> width0(width);
     for (uint32_t L = 2; L <= depth; ++L) {
         for (uint32_t k : slack) {
             if ((width[L] + 1) * count > round) break;
@@ -430,7 +480,6 @@ std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_
         }
     }
     const std::vector<uint32_t> filled(lev);
-    const std::vector<uint64_t> width1(width);
     // Trim: a level wider than a round whose last round is partly empty hands
     // that overflow (gates with slack, those with the most first) to the
     // earliest later level that has room below its own round boundary and
@@ -465,14 +514,31 @@ std::vector<uint32_t> balance_levels(const Circuit& c, const std::vector<uint32_
             }
         }
     }
-    double c_asap = 0, c_fill = 0, c_trim = 0;
-    for (uint32_t L = 1; L <= depth; ++L) {
-        c_asap += level_cost(width0[L] * count, round);
-        c_fill += level_cost(width1[L] * count, round);
-        c_trim += level_cost(width[L] * count, round);
+    // candidates: ASAP, filled, filled + trimmed, and list schedules with and
+    // without filling narrow levels; the cheapest by the cost model is kept
+    auto cost = [&](const std::vector<uint32_t>& l) {
+        std::vector<uint64_t> w(depth + 1, 0);
+        for (uint32_t x : l) w[x]++;
+        double t = 0;
+        for (uint32_t L = 1; L <= depth; ++L) t += level_cost(w[L] * count, round);
+        return t;
+    };
+    std::vector<std::vector<uint32_t>> cand;
+    cand.push_back(asap);
+    cand.push_back(filled);
+    cand.push_back(lev);
+    cand.push_back(list_schedule(c, alap, cons, depth, count, round, false));
+    cand.push_back(list_schedule(c, alap, cons, depth, count, round, true));
+    size_t best = 0;
+    double best_cost = cost(cand[0]);
+    for (size_t i = 1; i < cand.size(); ++i) {
+        const double t = cost(cand[i]);
+        if (t < best_cost) {
+            best_cost = t;
+            best = i;
+        }
     }
-    if (c_trim < c_fill && c_trim < c_asap) return lev;
-    return c_fill < c_asap ? filled : asap;
+    return cand[best];
 }
 
 }  // namespace fhe
@@ -489,8 +555,7 @@ extern "C" int fhe_circuit_schedule(int kind, uint32_t width, uint32_t rows, uin
     const Circuit c = build_circuit(kind, width, rows, cols);
     uint32_t depth = 0;
     const std::vector<uint32_t> asap = asap_levels(c, &depth);
-    const std::vector<uint32_t> lev =
-        c.has_compound() ? asap : balance_levels(c, asap, depth, count, 8 * (uint64_t)cu_count);
+    const std::vector<uint32_t> lev = balance_levels(c, asap, depth, count, 8 * (uint64_t)cu_count);
     if (levels) *levels = depth;
     if (level_gates) {
         if (max_levels < depth) return set_error(FHE_EINVAL, "fhe_circuit_schedule: %u levels do not fit", depth);

@@ -60,10 +60,8 @@ int build_plan(fhe_ctx* ctx, int kind, uint32_t w, uint32_t rows, uint32_t cols,
     const Circuit c = kind == kCustom ? ctx->circuits->custom.at(rows) : build_circuit(kind, w, rows, cols);
     uint32_t depth = 0;
     const std::vector<uint32_t> asap = asap_levels(c, &depth);
-    // compound nodes keep their ASAP levels (balancing moves single gates)
-    const bool pairs = c.has_compound();
-    const std::vector<uint32_t> glev =
-        pairs ? asap : balance_levels(c, asap, depth, count, 8 * (uint64_t)ctx->cu_count);
+    const bool pairs = c.has_compound();  // (balance_levels keeps such circuits at ASAP levels)
+    const std::vector<uint32_t> glev = balance_levels(c, asap, depth, count, 8 * (uint64_t)ctx->cu_count);
     const uint32_t nw = c.wires();
     // Local wire -> (region, index within instance) for one instance.
     std::vector<uint32_t> region(nw, kRegionPool), local(nw, 0);

@@ -79,7 +79,14 @@ int main(int argc, char** argv) {
             for (size_t count : {(size_t)1, (size_t)7, (size_t)1024}) {
                 const std::vector<uint32_t> lev = fhe::balance_levels(c, asap, depth, count, 2048);
                 CHECK(lev.size() == c.gates.size());
-                for (size_t k = 0; k < lev.size(); ++k) CHECK(lev[k] >= asap[k] && lev[k] <= depth);
+                const uint32_t base = c.na + c.nb;
+                for (size_t k = 0; k < lev.size(); ++k) {
+                    CHECK(lev[k] >= asap[k] && lev[k] <= depth);
+                    const fhe::Gate& g = c.gates[k];  // every input from an earlier level
+                    for (uint32_t in : {g.in0, g.in1, g.in2})
+                        if (in != fhe::kNoWire && in >= base) CHECK(lev[in - base] < lev[k]);
+                    if (g.second) CHECK(lev[k] == lev[k - 1]);  // a compound node stays whole
+                }
             }
             uint64_t g = 0;
             uint32_t lv = 0;

@@ -118,6 +118,19 @@ def test_argument_errors():
     assert L.fhe_debug_read_wires(None, 0, 16, 0, 0, 1, None, None, None, None, 0, None) == F.FHE_EINVAL
 
 
+def test_level_schedules_fill_launch_rounds():
+    """The balanced schedules of the paper-sized workloads: every gate once,
+    and whole launch rounds of 2,048 gates (eight per compute unit) nearly
+    full (the bound is the gate count over the round size)."""
+    for kind, w, count, rows, cols, most in [("add", 16, 1024, 0, 0, 37), ("mul", 32, 256, 0, 0, 356),
+                                            ("matvec", 16, 1, 64, 64, 1445)]:
+        widths = F.fhe_circuit_schedule(kind, w, count, 256, rows, cols)
+        assert sum(widths) == F.fhe_circuit_shape(kind, w, rows, cols)[0] * count
+        assert len(widths) == F.fhe_circuit_shape(kind, w, rows, cols)[1]
+        rounds = sum((x + 2047) // 2048 for x in widths if 2 * x > 2048)
+        assert rounds <= most, (kind, rounds)
+
+
 def test_circuit_shapes_match_oracle_gate_counts():
     for w in (1, 2, 5, 16, 32):
         assert F.fhe_circuit_shape("add", w)[0] == oracle.circuit_gate_count("add", w)
