@@ -189,6 +189,21 @@ int fhe_bootstrap_gate_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* i
 int fhe_bootstrap_gate3_batch(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
                               const uint32_t* in2, uint32_t* out, size_t count, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and words as fhe_bootstrap_gate_batch, with the scratch
+ * (extracted samples between blind rotation and key switching) in a fixed
+ * device array of the library instead of the context's buffer, so the call
+ * allocates nothing (no hipMalloc, no library allocation, no timing events).
+ * count is at most 4096 (FHE_EINVAL beyond).  The array is one per GPU,
+ * shared by every context on that GPU and kept until the process ends:
+ * calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race on it and must be ordered by the caller.  Outside graph
+ * capture the call is ordered after the context's last call on another
+ * stream, like the other calls; under capture the caller orders it. */
+int fhe_bootstrap_gate_batch_noalloc(fhe_ctx* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                                     uint32_t* out, size_t count, void* stream);
+
 /* Compound gates (Sec. V-A-3: two gates on the same inputs computed
  * together), here from ONE blind rotation: out0[g] = ops0[g](in0[g], in1[g])
  * and out1[g] = ops1[g](in0[g], in1[g]) for symmetric codes (FHE_AND, NAND,

@@ -76,6 +76,7 @@ _SIGS = {
     "fhe_bootstrap_gate3_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_bootstrap_lut_batch": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_bootstrap_compound_batch": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "fhe_bootstrap_gate_batch_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fhe_ctx_check": (C.c_int, [_vp]),
     "fhe_add_compound": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_uint32, _vp]),
     "fhe_matmul": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint32, C.c_uint32, _vp]),
@@ -312,6 +313,12 @@ def fhe_bootstrap_lut_batch(ctx, tv, inp, out, count, stream=None):
     """Programmable bootstrapping with test vector tv (device uint32[N])."""
     _check(lib().fhe_bootstrap_lut_batch(ctx.h, _dev(tv), _dev(inp), _dev(out), count, _stream(stream)),
            "fhe_bootstrap_lut_batch")
+
+
+def fhe_bootstrap_gate_batch_noalloc(ctx, ops, in0, in1, out, count, stream=None):
+    """fhe_bootstrap_gate_batch with the library's fixed scratch array (allocates nothing; count <= 4096)."""
+    _check(lib().fhe_bootstrap_gate_batch_noalloc(ctx.h, _dev(ops), _dev(in0), _dev(in1), _dev(out), count,
+                                                  _stream(stream)), "fhe_bootstrap_gate_batch_noalloc")
 
 
 def fhe_bootstrap_compound_batch(ctx, ops0, ops1, in0, in1, out0, out1, count, stream=None):

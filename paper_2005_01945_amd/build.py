@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libfhe_mi355x.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["kernels.hip", "runtime.cpp", "host_crypto.cpp", "circuits.cpp", "circuit_build.cpp", "serve.cpp",
-           "tuner.cpp"]
+           "tuner.cpp", "noalloc.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           # no packed-FP32 instructions anywhere in device code

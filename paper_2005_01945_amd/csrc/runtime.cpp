@@ -242,6 +242,10 @@ extern "C" int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out
     *ctx->err_host = 0;
     if ((e = hipHostGetDevicePointer((void**)&ctx->err_dev, ctx->err_host, 0)) != hipSuccess)
         return fail(e, "error word");
+    if ((rc = noalloc_scratch(device, &ctx->noalloc_scratch)) != FHE_OK) {
+        fhe_ctx_destroy(ctx);
+        return rc;
+    }
     if ((e = hipMalloc((void**)&ctx->twf, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->twi, 1024 * 8)) != hipSuccess) return fail(e, "twiddles");
     if ((e = hipMalloc((void**)&ctx->bkd, bkd_words * 8)) != hipSuccess) return fail(e, "bootstrapping key");

@@ -56,6 +56,9 @@ struct fhe_ctx {
     // kernels write through err_dev.
     uint32_t* err_host = nullptr;
     uint32_t* err_dev = nullptr;
+    // This device's fixed scratch array of the allocation-free entry point
+    // (noalloc.cpp), resolved when the context is created.
+    uint32_t* noalloc_scratch = nullptr;
 };
 
 namespace fhe {
@@ -90,6 +93,9 @@ int run_gate_batch(fhe_ctx* ctx, const dev::GateIO& io, size_t count, hipStream_
 // order_end records the call's completion on s.
 int order_begin(fhe_ctx* ctx, hipStream_t s);
 int order_end(fhe_ctx* ctx, hipStream_t s, int rc);
+// Device address of this device's fixed scratch array (noalloc.cpp); the
+// device must be current.
+int noalloc_scratch(int device, uint32_t** out);
 // FHE_EINVAL (and clears the word) when a kernel met an invalid gate code.
 int take_code_error(fhe_ctx* ctx);
 // run_gate_batch for an entry point: reports earlier invalid codes, orders
