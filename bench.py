@@ -146,6 +146,43 @@ def cpu_baseline(sk, config, sample_gates, single_gates, gates_per_step):
             "extrapolated_full_config_hours": full}
 
 
+def cpu_parallel_leg(sk, ck, config, sample_gates, gpu_value):
+    """The paper's CPU parallel framework (Sec. IV) on the host's cores: a
+    batch of level-1 gates of the benchmark's workload (one gate per thread),
+    16 add16 pairs (numbers across threads, bits in carry order) and one
+    16-bit multiplication (ANDs across threads, accumulation in order)."""
+    from paper_2005_01945_amd import cpupar
+    bk, ksk = ck.export()
+    cp = cpupar.CpuParallel(bk, ksk)
+    threads = host_threads()
+    ops, i0, i1 = level1_sample(sk, "add16" if config == "add16" else "mul32", sample_gates)
+    t0 = time.perf_counter()
+    cp.bootstrap(ops, i0, i1, threads=threads)
+    dt = time.perf_counter() - t0
+    rate = len(ops) / dt
+    wl = workloads.AddWorkload(count=16)
+    a, b = wl.operands()
+    ca, cb = sk.encrypt_uint(a, 16, nonce=7 << 48), sk.encrypt_uint(b, 16, nonce=(7 << 48) + 4096)
+    t0 = time.perf_counter()
+    r = cp.add(ca, cb, 16, threads=threads)
+    add_s = time.perf_counter() - t0
+    if not np.array_equal(sk.decrypt_uint(r, 16), (a + b) % (1 << 16)):
+        raise SystemExit("bench: CPU parallel additions decrypt wrongly")
+    ma, mb = workloads.uniform_uints(16, 1, 16), workloads.uniform_uints(17, 1, 16)
+    cma, cmb = sk.encrypt_uint(ma, 16, nonce=8 << 48), sk.encrypt_uint(mb, 16, nonce=(8 << 48) + 64)
+    t0 = time.perf_counter()
+    r = cp.mul(cma, cmb, 16, threads=threads)
+    mul_s = time.perf_counter() - t0
+    if sk.decrypt_uint(r, 16)[0] != (int(ma[0]) * int(mb[0])) % (1 << 16):
+        raise SystemExit("bench: CPU parallel multiplication decrypts wrongly")
+    return {"kind": "the paper's CPU parallel framework (Sec. IV): one gate per core, two-prime NTT products",
+            "gates_per_s": round(rate, 2), "cores": threads,
+            "sample": f"{len(ops)} level-1 gates of the benchmark's workload in {dt:.1f} s",
+            "add16_x16": {"s": round(add_s, 2), "adds_per_s": round(16 / add_s, 2)},
+            "mul16_latency_s": round(mul_s, 2),
+            "gpu_batched_over_cpu_parallel": round(gpu_value / rate, 1)}
+
+
 JOB_GATES = None
 
 
@@ -372,6 +409,8 @@ def main():
     ap.add_argument("--tune-max-width", type=int, default=4096,
                     help="autotune launch shapes up to this batch width before warmup (0 keeps the defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-parallel-gates", type=int, default=3072,
+                    help="gates of the CPU parallel framework leg (0 skips the leg)")
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs in the serving leg (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -653,6 +692,12 @@ def main():
         cpu = cpu_baseline(sk, args.config, args.cpu_sample_gates, args.cpu_single_gates, full)
         log(f"cpu baseline: {cpu}")
 
+    cpu_par = None
+    if not args.no_cpu_baseline and args.cpu_parallel_gates > 0:
+        log("CPU parallel framework (Sec. IV)")
+        cpu_par = cpu_parallel_leg(sk, ck, args.config, args.cpu_parallel_gates, value)
+        log(f"CPU parallel framework: {cpu_par}")
+
     shape = res.pop("_shape")
     dtype = ("u32 (Torus32) / i32 residues mod two 28-bit primes (NTT)" if shape[2] == 1
              else "u32 (Torus32) / u64 (NTT mod 2^64-2^32+1)")
@@ -672,7 +717,7 @@ def main():
         "key_switch_roofline": res["key_switch_roofline"],
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": res["timed_by_shape"]},
-        "roofline": res["roofline"], "cpu_baseline": cpu,
+        "roofline": res["roofline"], "cpu_baseline": cpu, "cpu_parallel_framework": cpu_par,
     }
     print(json.dumps(line), flush=True)
 

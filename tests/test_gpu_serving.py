@@ -194,3 +194,22 @@ def test_cancel_queued_job(env):
         assert F.fhe_serve_stats(srv)["pool_bytes_in_use"] == 0
     finally:
         srv.close()
+
+
+def test_device_allocation_failure_is_enomem(env):
+    """A server whose HBM budget exceeds the device (400 GiB against 288 GB)
+    fails with FHE_ENOMEM from its pool allocation, and the context keeps
+    working: a gate batch afterwards is bit-exact with the oracle."""
+    import torch
+    sk, ctx = env
+    with pytest.raises(F.FheError) as e:
+        F.Server(ctx, 400 << 30)
+    assert e.value.code == F.FHE_ENOMEM
+    a, b = workloads.truth_table_inputs()
+    c0, c1 = sk.encrypt_bits(a, nonce=3_900_000), sk.encrypt_bits(b, nonce=3_900_100)
+    ops = torch.tensor([F.NAND, F.XOR, F.AND, F.OR], dtype=torch.uint8, device="cuda")
+    d0, d1 = F.to_device(c0), F.to_device(c1)
+    out = torch.empty_like(d0)
+    F.fhe_bootstrap_gate_batch(ctx, ops, d0, d1, out, 4)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(F.to_host(out), oracle.Keys(0).bootstrap([F.NAND, F.XOR, F.AND, F.OR], c0, c1))
