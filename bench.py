@@ -444,6 +444,12 @@ def main():
     shapes = [[1 << b, *F.fhe_ctx_launch_config(ctx, 1 << b)] for b in range(16)]
     log(f"launch shapes [bucket width, waves/gate, gates/group, arith]: {shapes}")
 
+    # issue rates of the VALU instruction classes of the blind rotation (the
+    # per-class peaks behind the roofline's 39.32 T: one 32-bit operation per
+    # lane per cycle at 2.4 GHz)
+    valu_rates = {name: round(F.fhe_debug_valu_rate(op) / 1e12, 2) for op, name in enumerate(F.VALU_CLASSES)}
+    log(f"VALU issue rates (T lane-ops/s): {valu_rates}")
+
     # --- the measured workload (`value`) ---
     main_cfg = prepare_config(F, sk, ctx, args.config, stream)
     log(f"config {args.config}: {main_cfg['gates_per_step']} gates/step, {main_cfg['levels']} levels; "
@@ -717,7 +723,8 @@ def main():
         "key_switch_roofline": res["key_switch_roofline"],
         "launch_shapes": {"tuned": tuning_s is not None, "tuning_s": tuning_s, "buckets": shapes,
                           "timed_by_shape": res["timed_by_shape"]},
-        "roofline": res["roofline"], "cpu_baseline": cpu, "cpu_parallel_framework": cpu_par,
+        "roofline": res["roofline"], "valu_class_rates_tops": valu_rates,
+        "cpu_baseline": cpu, "cpu_parallel_framework": cpu_par,
     }
     print(json.dumps(line), flush=True)
 

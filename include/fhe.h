@@ -518,6 +518,15 @@ const char* fhe_last_error(void);
  * bk_i: uint32 [2l][2][N] (coefficient domain, rows r = 2j + p). */
 int fhe_debug_cmux(int device, int arith, const uint32_t* bk_i, int32_t abar, uint32_t* acc);
 
+/* Measurement entry: the issue rate of one VALU instruction class on
+ * `device`, in 32-bit lane operations per second (every lane of eight waves
+ * per SIMD runs 16 independent chains of the instruction; fastest of two
+ * timed runs): op 0 v_add_u32, 1 v_mul_lo_u32, 2 v_mad_i64_i32, 3
+ * v_mul_hi_u32, 4 v_bfe_i32, 5 v_permlane32_swap (two registers exchanged
+ * per instruction).  It is the per-class peak behind the blind rotation's
+ * roofline.  Synchronous; allocates and frees 2 MB.  EINVAL: op outside 0..5. */
+int fhe_debug_valu_rate(int device, int op, double* lane_ops_per_s);
+
 /* Test entries: the level schedule of the plan a circuit entry point runs on
  * this context, and the words its wires hold after a run, so that tests can
  * recompute sampled gates of a full-size circuit from the inputs the GPU gave

@@ -108,6 +108,7 @@ _SIGS = {
     "fhe_serve_destroy": (None, [_vp]),
     "fhe_last_error": (C.c_char_p, []),
     "fhe_debug_cmux": (C.c_int, [C.c_int, C.c_int, _vp, C.c_int32, _vp]),
+    "fhe_debug_valu_rate": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "fhe_debug_plan": (C.c_int, [_vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _vp, C.c_uint64,
                                  _vp, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]),
     "fhe_debug_read_wires": (C.c_int, [_vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _vp, _vp, _vp,
@@ -542,6 +543,16 @@ def fhe_debug_cmux(bk_i, abar, acc, device=0, arith=0):
     a = np.ascontiguousarray(acc, np.uint32).copy()
     _check(lib().fhe_debug_cmux(device, arith, pb, abar, a.ctypes.data), "fhe_debug_cmux")
     return a
+
+
+VALU_CLASSES = ["v_add_u32", "v_mul_lo_u32", "v_mad_i64_i32", "v_mul_hi_u32", "v_bfe_i32", "v_permlane32_swap"]
+
+
+def fhe_debug_valu_rate(op, device=0):
+    """Issue rate of VALU instruction class op (index into VALU_CLASSES), lane-ops/s."""
+    r = C.c_double()
+    _check(lib().fhe_debug_valu_rate(device, op, C.byref(r)), "fhe_debug_valu_rate")
+    return r.value
 
 
 def fhe_debug_plan(ctx, kind, width, count=1, rows=0, cols=0):

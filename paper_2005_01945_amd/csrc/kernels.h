@@ -96,5 +96,11 @@ hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32
 hipError_t launch_debug_cmux(const DeviceKeys& K, int arith, const uint64_t* bk_i, int32_t abar,
                              uint32_t* acc, hipStream_t s);
 
+// Issue-rate probe of VALU instruction class `op` (0 v_add_u32, 1
+// v_mul_lo_u32, 2 v_mad_i64_i32, 3 v_mul_hi_u32, 4 v_bfe_i32, 5
+// v_permlane32_swap): blocks x 256 threads, 64 x iters instructions per
+// lane; out holds blocks x 256 words.
+hipError_t launch_valu_probe(int op, uint32_t* out, uint32_t blocks, int iters, hipStream_t s);
+
 }  // namespace dev
 }  // namespace fhe

@@ -1408,7 +1408,56 @@ __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t*
     for (int k = threadIdx.x; k < 2 * N; k += 64) accg[k] = W.acc[k / N][k % N];
 }
 
+// Issue-rate probe of one VALU instruction class (the roofline's peak per
+// class): every lane runs 16 independent chains of the instruction, 64 per
+// iteration.  Only arithmetic instructions, no memory access but the final
+// store of each lane's sum into out[global thread index].
+template <int OP>
+__global__ __launch_bounds__(256) void k_valu_probe(uint32_t* __restrict__ out, int iters) {
+    uint32_t a[16];
+    uint64_t w[16];
+    const uint32_t b = threadIdx.x * 3u + 1u, c = threadIdx.x ^ 5u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        a[k] = threadIdx.x + k;
+        w[k] = (uint64_t)threadIdx.x * (k + 1);
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if constexpr (OP == 0) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (OP == 1) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (OP == 2)
+                    asm volatile("v_mad_i64_i32 %0, vcc, %1, %2, %0" : "+v"(w[k]) : "v"(b), "v"(c) : "vcc");
+                if constexpr (OP == 3) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (OP == 4) asm volatile("v_bfe_i32 %0, %0, %1, 10" : "+v"(a[k]) : "v"(c));
+                if constexpr (OP == 5)
+                    asm volatile("v_permlane32_swap_b32 %0, %1" : "+v"(a[k]), "+v"(a[(k + 1) & 15]));
+            }
+        }
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += a[k] + (uint32_t)w[k] + (uint32_t)(w[k] >> 32);
+    out[blockIdx.x * blockDim.x + threadIdx.x] = sum;
+}
+
 }  // namespace
+
+hipError_t launch_valu_probe(int op, uint32_t* out, uint32_t blocks, int iters, hipStream_t s) {
+    switch (op) {
+    case 0: hipLaunchKernelGGL(k_valu_probe<0>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case 1: hipLaunchKernelGGL(k_valu_probe<1>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case 2: hipLaunchKernelGGL(k_valu_probe<2>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case 3: hipLaunchKernelGGL(k_valu_probe<3>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case 4: hipLaunchKernelGGL(k_valu_probe<4>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    case 5: hipLaunchKernelGGL(k_valu_probe<5>, dim3(blocks), dim3(256), 0, s, out, iters); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_bk_prepare(const uint32_t* bk, uint64_t* bkd, const uint64_t* twf,
                              uint32_t n_lwe, hipStream_t s) {

@@ -80,6 +80,10 @@ DeviceGuard::~DeviceGuard() {
 }
 
 int hip_fail(hipError_t e, const char* what) {
+    // HIP keeps a failed call's code as the thread's last error; the launch
+    // checks read that word, so a refused allocation would otherwise be
+    // reported again by the next successful launch
+    (void)hipGetLastError();
     if (e == hipErrorOutOfMemory) return set_error(FHE_ENOMEM, "%s: out of device memory", what);
     return set_error(FHE_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
@@ -392,6 +396,36 @@ extern "C" int fhe_bootstrap_gate_plain(fhe_ctx* ctx, uint8_t op, const uint32_t
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? FHE_OK : hip_fail(e, "fhe_bootstrap_gate_plain");
+}
+
+extern "C" int fhe_debug_valu_rate(int device, int op, double* lane_ops_per_s) {
+    if (op < 0 || op > 5 || !lane_ops_per_s) return set_error(FHE_EINVAL, "fhe_debug_valu_rate: bad argument");
+    int rc = check_gfx950(device);
+    if (rc) return rc;
+    DeviceGuard guard(device);
+    const uint32_t blocks = 2048;  // eight waves per SIMD on 256 compute units
+    const int iters = 2000;
+    uint32_t* out = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    float best = 0;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // the first run warms up
+        e = hipEventRecord(ev[0], nullptr);
+        if (e == hipSuccess) e = dev::launch_valu_probe(op, out, blocks, iters, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (rep > 0 && (best == 0 || ms < best)) best = ms;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (out) (void)hipFree(out);
+    if (e != hipSuccess) return hip_fail(e, "fhe_debug_valu_rate");
+    *lane_ops_per_s = (double)blocks * 256 * iters * 64 / (best * 1e-3);
+    return FHE_OK;
 }
 
 extern "C" int fhe_debug_cmux(int device, int arith, const uint32_t* bk_i, int32_t abar, uint32_t* acc) {

@@ -1,6 +1,7 @@
 """GPU parity of gate bootstrapping: the HIP path through the C ABI against the
-CPU oracle, ciphertext word for ciphertext word (bit-exact: the NTT over
-p = 2^64 - 2^32 + 1 is exact, so no tolerance applies)."""
+CPU oracle, ciphertext word for ciphertext word (bit-exact: both NTT
+arithmetics, two 28-bit primes with CRT and 2^64 - 2^32 + 1, give the exact
+negacyclic products, so no tolerance applies)."""
 import numpy as np
 import pytest
 
@@ -284,3 +285,17 @@ def test_programmable_bootstrap_bit_exact(env):
     np.testing.assert_array_equal(got, K.bootstrap_lut(tv2, bits, threads=8))
     ph = K.phase(got).astype(np.int64) % (1 << 32)
     assert list((ph >> 29) & 3) == [f[m] for m in ms]
+
+
+def test_valu_class_rates_are_plausible():
+    """The per-class issue rates behind the roofline's peak: every class runs
+    at a positive rate below twice the nominal 39.32 T lane-ops/s (the most a
+    SIMD could issue with dual issue), and a class outside 0..5 is EINVAL."""
+    nominal = 256 * 64 * 2.4e9
+    rates = {name: F.fhe_debug_valu_rate(op) for op, name in enumerate(F.VALU_CLASSES)}
+    log(f"VALU rates: { {k: round(v / 1e12, 1) for k, v in rates.items()} }")
+    for name, r in rates.items():
+        assert 0.1 * nominal < r < 2.0 * nominal, (name, r)
+    with pytest.raises(F.FheError) as e:
+        F.fhe_debug_valu_rate(6)
+    assert e.value.code == F.FHE_EINVAL
