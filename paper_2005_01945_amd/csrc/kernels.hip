@@ -154,6 +154,38 @@ __device__ __forceinline__ const lds_u32* lds_column(const uint32_t* a, int t) {
     return p;
 }
 
+// Gadget digit of coefficient m of D = X^ai ACC - ACC for this half (digit
+// h of two: bits 22..31 for h = 0, 12..21 for h = 1), in [-512, 511], from
+// d = m - ai.  d needs no reduction: its bits 0..9 are d mod 1024 (the word
+// read) and its bit 10 tells whether d mod 2048 >= 1024 (X^N = -1: the word
+// is negated), for negative d too.  doff is the rounding offset of both
+// digits plus 2^(shift + 9), which makes the signed 10-bit field equal to
+// the unsigned field minus 512.
+__device__ __forceinline__ uint32_t digit_offset(int h) { return kDecompOffset + (1u << (31 - 10 * h)); }
+
+__device__ __forceinline__ int32_t rotated_digit(const uint32_t* a, uint32_t own, int d, uint32_t doff,
+                                                 int shift) {
+    const uint32_t v = a[d & 1023];
+    const uint32_t sgn = (uint32_t)__builtin_amdgcn_sbfe(d, 10, 1);
+    const uint32_t D = ((v ^ sgn) - sgn) - own;
+    return __builtin_amdgcn_sbfe((int32_t)(D + doff), shift, 10);
+}
+
+// The same from d4 = 4 d and the LDS byte address abase of the polynomial,
+// a multiple of 4096, so that the word's address is one AND-OR.  The sign
+// mask comes from an opaque bit-field extract: the optimiser would otherwise
+// rebuild -sgn as a second, zero-extended bit and spend an extra instruction
+// per coefficient on it.
+__device__ __forceinline__ int32_t rotated_digit_q(uint32_t abase, uint32_t own, int d4, uint32_t doff,
+                                                   int shift) {
+    const lds_u32* p = (const lds_u32*)(uintptr_t)(((uint32_t)d4 & 0xFFCu) | abase);
+    const uint32_t v = *p;
+    uint32_t sgn;
+    asm("v_bfe_i32 %0, %1, 12, 1" : "=v"(sgn) : "v"(d4));
+    const uint32_t k = (doff - own) - sgn;
+    return __builtin_amdgcn_sbfe((int32_t)((v ^ sgn) + k), shift, 10);
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -224,14 +256,14 @@ __device__ __forceinline__ uint64_t partner64(uint64_t v, int h) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Per-wave LDS: the accumulator (two polynomials of 1024 words) and one
-// 32 x 32 transpose tile of 32-bit words per half (TW words: 32 x 32 with an
-// XOR swizzle for the Goldilocks path, 32 x 33 padded rows for the two-prime
-// path).  16 KB (16.5 KB).
+// Per-wave LDS, as views into the block's arrays: the accumulator (two
+// polynomials of 1024 words) and one 32 x 32 transpose tile of 32-bit words
+// per half (TW words: 32 x 32 with an XOR swizzle for the Goldilocks path,
+// 32 x 33 padded rows for the two-prime path).  16 KB (16.5 KB).
 template <int TW>
 struct WaveLdsT {
-    uint32_t acc[2][1024];
-    uint32_t tile[2][TW];
+    uint32_t (&acc)[2][1024];
+    uint32_t (&tile)[2][TW];
 };
 using WaveLds = WaveLdsT<32 * 32>;
 
@@ -239,27 +271,32 @@ template <int A>
 constexpr int kTileWords = A == 1 ? 32 * 33 : 32 * 32;
 
 // Shared-memory footprint of a block of WPB one-wave gates: twiddles plus one
-// per-wave area per wave (WPB = 4 with the Goldilocks path: 80 KB, so two
-// blocks fit a CU's 160 KB, i.e. two waves per SIMD; WPB = 8 with the
-// two-prime path: 146 KB, one block of two waves per SIMD).
+// accumulator and one pair of tiles per wave (WPB = 4 with the Goldilocks
+// path: 80 KB, so two blocks fit a CU's 160 KB, i.e. two waves per SIMD;
+// WPB = 8 with the two-prime path: 148 KB, one block of two waves per SIMD).
+// Every accumulator polynomial starts at a multiple of 4 KB (rotated_digit_q).
 template <int WPB, int A>
-struct BlockLds {
+struct alignas(4096) BlockLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
-    WaveLdsT<kTileWords<A>> w[WPB];
+    uint32_t acc[WPB][2][1024];
+    uint32_t tile[WPB][2][kTileWords<A>];
 };
+using BlockLds81 = BlockLds<8, 1>;
+static_assert(offsetof(BlockLds81, acc) % 4096 == 0, "accumulators must be 4 KB aligned");
 
 // Shared memory of one gate bootstrapped by two waves (56 KB): wave w runs
 // pass w of every CMux; wave 1 hands its multiply-accumulate result to wave 0
 // through `part`, and wave 0 finishes the step.
 template <int A>
-struct PairLds {
+struct alignas(4096) PairLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
     uint32_t acc[2][1024];
     uint32_t tile[2][2][kTileWords<A>];  // [wave][half]
     uint64_t part[32][64];               // [register q][lane]
 };
+static_assert(offsetof(PairLds<1>, acc) % 4096 == 0, "accumulators must be 4 KB aligned");
 
 // Shared memory of one gate bootstrapped by four waves (two-prime arithmetic
 // only, 74 KB): wave w = 2 hp + prime runs pass hp in that prime; the pass-1
@@ -523,7 +560,11 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
                                             int lane, uint64_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
+    const uint32_t doff = digit_offset(h);
     const lds_u32* am = lds_column(a, t);
+    const uint32_t abase = (uint32_t)(uintptr_t)(const lds_u32*)a;
+    int d4 = 4 * (t - ai);  // opaque: each pass forms its own addresses instead of keeping them
+    asm volatile("" : "+v"(d4));
     const uint32_t* bk0 = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192;
     const uint32_t* bk1 = bk0 + 4096;
     KeyWindow<W> kw;
@@ -535,12 +576,7 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
         sched_fence();
 #pragma unroll
         for (int q = 8 * c; q < 8 * c + 8; ++q) {
-            const int m = t + 32 * q;
-            const int s = (m - ai) & 2047;
-            const uint32_t v = a[s & 1023];
-            const uint32_t rot = (s & 1024) ? 0u - v : v;
-            const uint32_t D = rot - am[32 * q];
-            x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
+            x[q] = rotated_digit_q(abase, am[32 * q], d4 + 128 * q, doff, shift);
         }
 #pragma unroll
         for (int j = 4 * c; j < 4 * c + 4; ++j)
@@ -578,7 +614,10 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
                                              int lane, int32_t (&mac)[32]) {
     const int h = lane >> 5, t = lane & 31;
     const int shift = 22 - 10 * h;
+    const uint32_t doff = digit_offset(h);
     const lds_u32* am = lds_column(a, t);
+    int d0 = t - ai;  // opaque: the pass forms its own indices instead of keeping them
+    asm volatile("" : "+v"(d0));
     const uint32_t* bk = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192 + I * 4096;
     KeyWindow<W> kw;
     prefetch_q<W>(bk, lane, kw);
@@ -588,12 +627,7 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
         sched_fence();
 #pragma unroll
         for (int q = 8 * c; q < 8 * c + 8; ++q) {
-            const int m = t + 32 * q;
-            const int s = (m - ai) & 2047;
-            const uint32_t v = a[s & 1023];
-            const uint32_t rot = (s & 1024) ? 0u - v : v;
-            const uint32_t D = rot - am[32 * q];
-            x[q] = (int32_t)(((D + kDecompOffset) >> shift) & 1023u) - 512;
+            x[q] = rotated_digit(a, am[32 * q], d0 + 32 * q, doff, shift);
         }
     }
     sched_fence();
@@ -621,22 +655,35 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
 // ACC (half h: polynomial h) += the column given by its residues x0, x1
 // (register r: coefficient t + 32 brv5(r)).
 // Registers 8C..8C+7 of the CRT update below (x0, x1: those registers'
-// residues).
+// residues).  The constants come in scalar registers (crt_consts), so that
+// the optimiser keeps the products as multiplies instead of expanding them
+// into shifts and adds of the 2^28 - 2^16 + ... forms of the primes.
+struct CrtConsts {
+    int32_t q0, nq1, cq;  // q0, -q1, q0^-1 R mod q1 (centred)
+};
+
+__device__ __forceinline__ CrtConsts crt_consts() {
+    constexpr int32_t cq = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
+    return {mq::sconst<(int32_t)mq::Mod<0>::q>(), mq::sconst<-(int32_t)mq::Mod<1>::q>(), mq::sconst<cq>()};
+}
+
 template <int C>
 __device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[8],
-                                            const int32_t (&x1)[8], int lane) {
+                                            const int32_t (&x1)[8], int lane, const CrtConsts& K) {
     const int h = lane >> 5, t = lane & 31;
     uint32_t* mine = acc[h] + t;
-    constexpr int32_t q0 = (int32_t)mq::Mod<0>::q, q1 = (int32_t)mq::Mod<1>::q;
-    constexpr int32_t cq = mq::Mod<1>::rform(mq::powmod(mq::Mod<0>::q, mq::Mod<1>::q - 2, mq::Mod<1>::q));
     int32_t d[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) d[k] = x1[k] - x0[k];
+    for (int k = 0; k < 8; ++k) {
+        d[k] = x1[k];
+        asm volatile("" : "+v"(d[k]));  // keeps the subtraction 32-bit (the optimiser folds it into
+        d[k] -= x0[k];                    // the preceding Montgomery reduction as a 64-bit one)
+    }
     sched_fence();
     int64_t p[8];
     int32_t m[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) p[k] = (int64_t)d[k] * cq;
+    for (int k = 0; k < 8; ++k) p[k] = (int64_t)d[k] * K.cq;
     sched_fence();
 #pragma unroll
     for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<1>::qinv);
@@ -645,25 +692,24 @@ __device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int3
 #pragma unroll
     for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * C + k)];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int32_t tq = (int32_t)((p[k] - (int64_t)m[k] * q1) >> 32);
-        tq += tq < -(q1 / 2) ? q1 : 0;
-        tq -= tq > q1 / 2 ? q1 : 0;
-        d[k] = tq;
-    }
+    for (int k = 0; k < 8; ++k) d[k] = (int32_t)((p[k] + (int64_t)m[k] * K.nq1) >> 32);
     sched_fence();
 #pragma unroll
-    for (int k = 0; k < 8; ++k) mine[32 * brv5(8 * C + k)] = old[k] + (uint32_t)x0[k] + (uint32_t)q0 * (uint32_t)d[k];
+    for (int k = 0; k < 8; ++k) mine[32 * brv5(8 * C + k)] = old[k] + (uint32_t)x0[k] + (uint32_t)K.q0 * (uint32_t)d[k];
     sched_fence();
 }
 
 // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 ->
-// V mod 2^32: t = (v1 - v0) q0^-1 mod q1, centred, gives V = v0 + q0 t
-// exactly (|v0 + q0 t| < q0 + q0 q1 / 2 and V is the only value of that size
-// in its class); ACC[h][t + 32 brv5(r)] += V.  Eight registers at a time, in
-// phases.
+// V mod 2^32: V = v0 + q0 T with T = (v1 - v0) q0^-1 mod q1 taken in
+// (-q1/2, q1/2); in fact |T| <= (2^52 + q0) / q0 < 2^24 + 2^13.  The Montgomery
+// product t = mont((v1 - v0) cq), cq = q0^-1 R mod q1 centred, is that T
+// without any correction: |v1 - v0| < 2^29 and |cq| <= q1/2 < 2^27 bound the
+// product by 2^56, so |t| < 2^56 / 2^32 + q1/2 < 2^24 + q1/2, and t and T,
+// congruent modulo q1, differ by less than 2^25 + 2^13 + q1/2 < q1: t = T.
+// ACC[h][t + 32 brv5(r)] += V.  Eight registers at a time, in phases.
 __device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
                                              const int32_t (&x1)[32], int lane) {
+    const CrtConsts K = crt_consts();
     mq::static_for<0, 4>([&](auto C_) {
         constexpr int c = decltype(C_)::value;
         int32_t a0[8], a1[8];
@@ -672,7 +718,7 @@ __device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int
             a0[k] = x0[8 * c + k];
             a1[k] = x1[8 * c + k];
         }
-        crt_chunk_q<c>(acc, a0, a1, lane);
+        crt_chunk_q<c>(acc, a0, a1, lane, K);
     });
 }
 
@@ -994,7 +1040,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int h = lane >> 5, t = lane & 31;
     uint32_t ab[8];
     const int bbar = gate_prologue(io, g, lane, ab);
-    auto& W = S.w[wave];
+    WaveLdsT<kTileWords<A>> W{S.acc[wave], S.tile[wave]};
     acc_init(W.acc, bbar, h, t, io.tv, gate_mu(io, g));
     wave_lds_sync();
 
@@ -1084,13 +1130,13 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     a0[k] = x[k];
                     a1[k] = part1[k * 64 + lane];
                 }
-                crt_chunk_q<0>(S.acc, a0, a1, lane);
+                crt_chunk_q<0>(S.acc, a0, a1, lane, crt_consts());
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     a0[k] = x[8 + k];
                     a1[k] = part1[(8 + k) * 64 + lane];
                 }
-                crt_chunk_q<1>(S.acc, a0, a1, lane);
+                crt_chunk_q<1>(S.acc, a0, a1, lane, crt_consts());
             } else {
                 int32_t a0[8], a1[8];
 #pragma unroll
@@ -1098,13 +1144,13 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     a0[k] = part0[(16 + k) * 64 + lane];
                     a1[k] = x[16 + k];
                 }
-                crt_chunk_q<2>(S.acc, a0, a1, lane);
+                crt_chunk_q<2>(S.acc, a0, a1, lane, crt_consts());
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     a0[k] = part0[(24 + k) * 64 + lane];
                     a1[k] = x[24 + k];
                 }
-                crt_chunk_q<3>(S.acc, a0, a1, lane);
+                crt_chunk_q<3>(S.acc, a0, a1, lane, crt_consts());
             }
             __syncthreads();  // ACC updated
             bk += 2 * 32 * 2 * 64;
@@ -1201,10 +1247,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 a1[k] = wave == 1 ? x[8 + k] : S.part[1][8 * wave + k][lane];
             }
             switch (wave) {
-            case 0: crt_chunk_q<0>(S.acc, a0, a1, lane); break;
-            case 1: crt_chunk_q<1>(S.acc, a0, a1, lane); break;
-            case 2: crt_chunk_q<2>(S.acc, a0, a1, lane); break;
-            default: crt_chunk_q<3>(S.acc, a0, a1, lane); break;
+            case 0: crt_chunk_q<0>(S.acc, a0, a1, lane, crt_consts()); break;
+            case 1: crt_chunk_q<1>(S.acc, a0, a1, lane, crt_consts()); break;
+            case 2: crt_chunk_q<2>(S.acc, a0, a1, lane, crt_consts()); break;
+            default: crt_chunk_q<3>(S.acc, a0, a1, lane, crt_consts()); break;
             }
         }
         __syncthreads();  // ACC updated
@@ -1393,17 +1439,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare_q(const uint32_t* 
 template <int A>
 __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t* __restrict__ bk_i,
                                                    int32_t abar, uint32_t* __restrict__ accg) {
-    __shared__ uint64_t stw[2][32 * 32];
-    __shared__ WaveLdsT<kTileWords<A>> W;
+    __shared__ BlockLds<1, A> S;
+    WaveLdsT<kTileWords<A>> W{S.acc[0], S.tile[0]};
     const uint64_t* twf = Arith<A>::twf(K);
     const uint64_t* twi = Arith<A>::twi(K);
     for (int k = threadIdx.x; k < 1024; k += 64) {
-        stw[0][k] = twf[k];
-        stw[1][k] = twi[k];
+        S.twf[k] = twf[k];
+        S.twi[k] = twi[k];
     }
     for (int k = threadIdx.x; k < 2 * N; k += 64) W.acc[k / N][k % N] = accg[k];
     __syncthreads();
-    Arith<A>::template step<kKeyWindow>(W, abar, bk_i, stw[0], stw[1], threadIdx.x);
+    Arith<A>::template step<kKeyWindow>(W, abar, bk_i, S.twf, S.twi, threadIdx.x);
     __syncthreads();
     for (int k = threadIdx.x; k < 2 * N; k += 64) accg[k] = W.acc[k / N][k % N];
 }
