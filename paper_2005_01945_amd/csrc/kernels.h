@@ -54,7 +54,7 @@ struct DeviceKeys {
     const uint64_t* twf;      // forward twiddles [32][32]
     const uint64_t* twi;      // inverse twiddles (with N^-1) [32][32]
     // Two-prime NTT: BK residues (Montgomery form, 32-bit words)
-    // [n][hp][prime][q][digit][64 lanes], and twiddle tables int32
+    // [n][hp][prime][q / 2][64 lanes][q % 2][digit], and twiddle tables int32
     // [prime][32][32] (8 KB each, read as 1024 uint64).
     const uint64_t* bkq;
     const uint64_t* twfq;

@@ -259,7 +259,7 @@ __device__ __forceinline__ uint64_t partner64(uint64_t v, int h) {
 // Per-wave LDS, as views into the block's arrays: the accumulator (two
 // polynomials of 1024 words) and one 32 x 32 transpose tile of 32-bit words
 // per half (TW words: 32 x 32 with an XOR swizzle for the Goldilocks path,
-// 32 x 33 padded rows for the two-prime path).  16 KB (16.5 KB).
+// 32 x 36 padded rows for the two-prime path).  16 KB (17 KB).
 template <int TW>
 struct WaveLdsT {
     uint32_t (&acc)[2][1024];
@@ -268,7 +268,7 @@ struct WaveLdsT {
 using WaveLds = WaveLdsT<32 * 32>;
 
 template <int A>
-constexpr int kTileWords = A == 1 ? 32 * 33 : 32 * 32;
+constexpr int kTileWords = A == 1 ? 32 * 36 : 32 * 32;
 
 // Shared-memory footprint of a block of WPB one-wave gates: twiddles plus one
 // accumulator and one pair of tiles per wave (WPB = 4 with the Goldilocks
@@ -306,7 +306,7 @@ struct QuadLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
     uint32_t acc[2][1024];
-    uint32_t tile[4][2][32 * 33];  // [wave][half]
+    uint32_t tile[4][2][32 * 36];  // [wave][half]
     int32_t part[2][32][64];       // [prime][register][lane]
 };
 
@@ -397,7 +397,8 @@ __device__ __forceinline__ void cmux_step(WaveLds& W, int ai, const uint64_t* __
 // multiply-accumulate value holds the prime-0 residue in its low word and the
 // prime-1 residue in its high word (signed 32-bit each); BK is in the
 // Montgomery form c R mod q with |c| <= q/2, in the 32-bit layout
-// [i][hp][prime][q][digit][lane 32c + t].
+// [i][hp][prime][q / 2][lane 32c + t][q % 2][digit]: the four words of a
+// lane's register pair (2 registers x 2 digits) are one 16-byte load.
 // Twiddle tables (LDS, int32): forward [prime][q][t] = psi^(t(2 brv5(q)+1)) R,
 // inverse [prime][r][j] = psi^(-r(2j+1)) N^-1 R.
 // ---------------------------------------------------------------------------
@@ -408,25 +409,35 @@ __device__ __forceinline__ uint64_t pack2(int32_t a, int32_t b) {
     return ((uint64_t)(uint32_t)b << 32) | (uint32_t)a;
 }
 
-// 32 x 32 transpose of 32-bit values through a tile of 32 rows of 33 words:
-// element (row, col) at row*33 + col.  Row writes and column reads are both
-// free of bank conflicts, and every address is a per-lane base (t or 33 t)
-// plus a constant, so no per-register address is kept live.  Before: register
-// k holds (row wr(k), col t); after: register k holds (row t, col rd(k)).
-template <class WR, class RD>
-__device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr, RD rd) {
+// 32 x 32 transpose of 32-bit values through a tile of 32 rows of 36 words:
+// element (row, col) at row*36 + col.  Column writes hit 32 consecutive
+// words per row; each lane reads its row as eight 16-byte loads, and the
+// rows' 4-word skew spreads eight lanes' loads over all 32 banks.  Every
+// address is a per-lane base (t or 36 t) plus a constant, so no per-register
+// address is kept live.  Before: register k holds (row wr(k), col t); after:
+// register k holds (row t, col k).
+template <class WR>
+__device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, int t, WR wr) {
     uint32_t* col = tile + t;  // this lane's column
     // This lane's row, as an LDS address opaque to the optimiser: otherwise
     // it hoists one base address per pair of reads out of the CMux loop and
     // spills them.  (Kept in the LDS address space so that the reads are LDS
     // instructions, which wait on LDS traffic only.)
-    lds_u32* row = (lds_u32*)(tile + 33 * t);
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) v4u lds_u4;
+    lds_u4* row = (lds_u4*)(tile + 36 * t);
     asm volatile("" : "+v"(row));
 #pragma unroll
-    for (int k = 0; k < 32; ++k) col[wr(k) * 33] = (uint32_t)x[k];
+    for (int k = 0; k < 32; ++k) col[wr(k) * 36] = (uint32_t)x[k];
     wave_lds_sync();
 #pragma unroll
-    for (int k = 0; k < 32; ++k) x[k] = (int32_t)row[rd(k)];
+    for (int g = 0; g < 8; ++g) {
+        const v4u v = row[g];
+        x[4 * g + 0] = (int32_t)v.x;
+        x[4 * g + 1] = (int32_t)v.y;
+        x[4 * g + 2] = (int32_t)v.z;
+        x[4 * g + 3] = (int32_t)v.w;
+    }
     wave_lds_sync();
 }
 
@@ -466,7 +477,7 @@ template <int I>
 __device__ __forceinline__ void ntt1024_fwd_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twf, int t) {
     mq::ntt32<I, mq::kNeg, 1>(x);
     table_mul_q<I>(x, twf, t);
-    transpose32_w(x, tile, t, [](int q) { return brv5(q); }, [](int r) { return r; });
+    transpose32_w(x, tile, t, [](int q) { return brv5(q); });
     mq::ntt32<I, mq::kCycFwd, 1>(x);
 }
 
@@ -476,7 +487,7 @@ template <int I>
 __device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, const int32_t* twi, int t) {
     mq::ntt32<I, mq::kDitInv, 2>(x);
     table_mul_q<I>(x, twi, t);
-    transpose32_w(x, tile, t, [](int r) { return r; }, [](int j) { return j; });
+    transpose32_w(x, tile, t, [](int r) { return r; });
     mq::ntt32<I, mq::kCycInv, 1>(x);
     // negacyclic twist psi^(-32 q) of output q = brv5(r): rho^(-q)
     mq::static_for<0, 4>([&](auto C_) {
@@ -493,7 +504,7 @@ __device__ __forceinline__ void ntt1024_inv_q(int32_t (&x)[32], uint32_t* tile, 
 // Multiply-accumulate of prime I for pass HP: column h of the products of the
 // two digit transforms (r0: digit 0, half 0's; r1: digit 1, half 1's, both
 // obtained with one v_permlane32_swap) with BK rows 2HP and 2HP + 1.
-// bk: the prime-I plane of BK_i for pass HP, [q][digit][64 lanes] words, in
+// bk: the prime-I plane of BK_i for pass HP, [q / 2][64 lanes][q % 2][digit] words, in
 // 8 chunks of 4 registers (8 words).  Key loads run W chunks ahead of their
 // use; the first W chunks (`pre`) were issued before the forward transform.
 template <int W>
@@ -506,7 +517,13 @@ __device__ __forceinline__ void prefetch_q(const uint32_t* __restrict__ bk, int 
 #pragma unroll
     for (int c = 0; c < W; ++c)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) kw.w[c][k] = bk[(c * 8 + k) * 64 + lane];
+        for (int u = 0; u < 2; ++u) {
+            const uint4 v = *reinterpret_cast<const uint4*>(bk + ((2 * c + u) * 64 + lane) * 4);
+            kw.w[c][4 * u + 0] = v.x;
+            kw.w[c][4 * u + 1] = v.y;
+            kw.w[c][4 * u + 2] = v.z;
+            kw.w[c][4 * u + 3] = v.w;
+        }
 }
 
 template <int I, bool ACCUM, int W>
@@ -517,7 +534,13 @@ __device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __
         constexpr int c = decltype(C_)::value;
         if constexpr (c + W < 8) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) kw.w[(c + W) % R][k] = bk[((c + W) * 8 + k) * 64 + lane];
+            for (int u = 0; u < 2; ++u) {
+                const uint4 v = *reinterpret_cast<const uint4*>(bk + ((2 * (c + W) + u) * 64 + lane) * 4);
+                kw.w[(c + W) % R][4 * u + 0] = v.x;
+                kw.w[(c + W) % R][4 * u + 1] = v.y;
+                kw.w[(c + W) % R][4 * u + 2] = v.z;
+                kw.w[(c + W) % R][4 * u + 3] = v.w;
+            }
         }
         sched_fence();
         // phases: exchanges, first products, second products, quotients,
@@ -552,7 +575,7 @@ __device__ __forceinline__ void mac_q(const int32_t (&x)[32], const uint32_t* __
 // ACC_HP (half h: digit h), then for each prime in turn its transform and
 // multiply-accumulate of column h.  The digits wait for the second prime
 // packed two to a register.  mac: low word prime 0, high word prime 1, each
-// |.| < q per pass.  bk_i: BK_i, [hp][prime][q][digit][64 lanes] words.
+// |.| < q per pass.  bk_i: BK_i, [hp][prime][q / 2][64 lanes][q % 2][digit] words.
 // W: key-load window in chunks (8: all loads issued before the transform).
 template <int HP, bool ACCUM, int W>
 __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, int ai,
@@ -723,7 +746,7 @@ __device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int
 }
 
 template <int KW>
-__device__ __forceinline__ void cmux_step_q(WaveLdsT<32 * 33>& W, int ai, const uint64_t* __restrict__ bk_i,
+__device__ __forceinline__ void cmux_step_q(WaveLdsT<32 * 36>& W, int ai, const uint64_t* __restrict__ bk_i,
                                             const int32_t* twf, const int32_t* twi, int lane) {
     const int h = lane >> 5;
     uint64_t mac[32];
@@ -766,7 +789,7 @@ struct Arith<1> {
     __host__ __device__ static const uint64_t* twf(const DeviceKeys& K) { return K.twfq; }
     __host__ __device__ static const uint64_t* twi(const DeviceKeys& K) { return K.twiq; }
     template <int KW>
-    __device__ __forceinline__ static void step(WaveLdsT<32 * 33>& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
+    __device__ __forceinline__ static void step(WaveLdsT<32 * 36>& W, int ai, const uint64_t* bk_i, const uint64_t* twf,
                                 const uint64_t* twi, int lane) {
         cmux_step_q<KW>(W, ai, bk_i, reinterpret_cast<const int32_t*>(twf),
                     reinterpret_cast<const int32_t*>(twi), lane);
@@ -1386,7 +1409,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare(const uint32_t* __
 }
 
 // BK -> two-prime NTT domain in the layout cmux_pass_q reads:
-// bkq[i][hp][prime][q][digit][lane 32c + t] (32-bit words) for row
+// bkq[i][hp][prime][q / 2][lane 32c + t][q % 2][digit] (32-bit words) for row
 // r = 2hp + digit, column c, each residue in Montgomery form and centred
 // (|.| <= q/2).
 template <int I>
@@ -1427,11 +1450,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_bk_prepare_q(const uint32_t* 
     bk_residue<1>(bk, poly, t, x1, &tiles[wave][h][0], stw + 1024);
     const uint32_t i = poly / 8, r = (poly / 2) % 4, c = poly % 2;
     const uint32_t hp = r >> 1, digit = r & 1;
-    uint32_t* dst = reinterpret_cast<uint32_t*>(bkq) + (size_t)i * 16384 + (size_t)hp * 8192 + 32 * c + t;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(bkq) + (size_t)i * 16384 + (size_t)hp * 8192;
+    const int lw = 32 * c + t;
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        dst[(q * 2 + digit) * 64] = (uint32_t)x0[q];
-        dst[4096 + (q * 2 + digit) * 64] = (uint32_t)x1[q];
+        dst[((q >> 1) * 64 + lw) * 4 + (q & 1) * 2 + digit] = (uint32_t)x0[q];
+        dst[4096 + ((q >> 1) * 64 + lw) * 4 + (q & 1) * 2 + digit] = (uint32_t)x1[q];
     }
 }
 
