@@ -172,18 +172,16 @@ __device__ __forceinline__ int32_t rotated_digit(const uint32_t* a, uint32_t own
 }
 
 // The same from d4 = 4 d and the LDS byte address abase of the polynomial,
-// a multiple of 4096, so that the word's address is one AND-OR.  The sign
-// mask comes from an opaque bit-field extract: the optimiser would otherwise
-// rebuild -sgn as a second, zero-extended bit and spend an extra instruction
-// per coefficient on it.
+// a multiple of 4096, so that the word's address is one AND-OR.  The
+// negation is written (v + sgn) ^ sgn, which needs the mask alone (the form
+// (v ^ sgn) - sgn makes the optimiser build -sgn as a second, zero-extended
+// bit): bit-field extract, add, XOR-add, subtract per coefficient.
 __device__ __forceinline__ int32_t rotated_digit_q(uint32_t abase, uint32_t own, int d4, uint32_t doff,
                                                    int shift) {
     const lds_u32* p = (const lds_u32*)(uintptr_t)(((uint32_t)d4 & 0xFFCu) | abase);
     const uint32_t v = *p;
-    uint32_t sgn;
-    asm("v_bfe_i32 %0, %1, 12, 1" : "=v"(sgn) : "v"(d4));
-    const uint32_t k = (doff - own) - sgn;
-    return __builtin_amdgcn_sbfe((int32_t)((v ^ sgn) + k), shift, 10);
+    const uint32_t sgn = (uint32_t)__builtin_amdgcn_sbfe(d4, 12, 1);
+    return __builtin_amdgcn_sbfe((int32_t)(((v + sgn) ^ sgn) + (doff - own)), shift, 10);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -1288,7 +1286,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
 // Key switching N -> n: out = (0, b') - sum_{i,j} KSK[i][j][d_ij], d_ij the
 // j-th base-4 digit of a'_i rounded to 16 bits.  One wave per gate; lane l
-// owns output words 8l .. 8l+7 and gathers 2 KB rows with 16-byte loads.
+// owns output words 8l .. 8l+7 and gathers 2 KB rows with 16-byte loads; a
+// zero digit (a quarter of them) skips its row.
 __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, GateIO io,
                                                               const uint32_t* __restrict__ big,
                                                               uint32_t count) {
@@ -1301,7 +1300,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
     uint32_t acc[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) acc[e] = (8 * lane + e == NLWE) ? src[N] : 0u;
-    const uint4* zero = reinterpret_cast<const uint4*>(K.zero_row);
 #pragma unroll 1
     for (int i0 = 0; i0 < N; i0 += 64) {
         const uint32_t digits = (src[i0 + lane] + (1u << 15)) >> 16;
@@ -1312,8 +1310,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
 #pragma unroll
             for (int j = 0; j < (int)kKsT; ++j) {
                 const uint32_t d = (dd >> (14 - 2 * j)) & 3u;
-                const uint4* row = d ? reinterpret_cast<const uint4*>(K.ksk + (rowbase + 3 * j + d - 1) * kKskRowWords)
-                                     : zero;
+                if (d == 0) continue;  // uniform over the wave: a zero digit selects no row
+                const uint4* row = reinterpret_cast<const uint4*>(K.ksk + (rowbase + 3 * j + d - 1) * kKskRowWords);
                 const uint4 v0 = row[2 * lane], v1 = row[2 * lane + 1];
                 acc[0] -= v0.x; acc[1] -= v0.y; acc[2] -= v0.z; acc[3] -= v0.w;
                 acc[4] -= v1.x; acc[5] -= v1.y; acc[6] -= v1.z; acc[7] -= v1.w;
@@ -1329,11 +1327,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
 // coefficients 128w .. 128w + 127, the eight partial sums meet in LDS and
 // wave 0 writes the result.  Eight times the waves in flight of the one-wave
 // kernel hides the latency of the row gathers; measured faster at every
-// batch width except 2,561 .. 4,096 gates (16,384 gates: 8.5 vs 17.3 ms for
-// one wave per gate, and 12.4 ms when the rows of a coefficient are staged
-// in LDS once per workgroup of eight gates).
+// batch width except 2,305 .. 6,144 gates, where the one-wave kernel, which
+// skips zero digits, wins (6,144 gates: 2.26 vs 3.20 ms; 8,192: 6.05 vs
+// 4.27; 16,384 gates: 8.5 vs 17.3 ms, and 12.4 ms when the rows of a
+// coefficient are staged in LDS once per workgroup of eight gates).  Zero digits read the all-zero
+// row here instead of branching past it: a wave-uniform skip serialises the
+// eight row loads of a coefficient (16,384 gates: 21.3 vs 8.5 ms).
 constexpr int kKsSplitWaves = 8;
-constexpr uint32_t kKsOneWaveMin = 2561, kKsOneWaveMax = 4096;
+constexpr uint32_t kKsOneWaveMin = 2305, kKsOneWaveMax = 6144;
 
 __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceKeys K, GateIO io,
                                                                         const uint32_t* __restrict__ big,
