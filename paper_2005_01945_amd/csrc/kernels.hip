@@ -1323,23 +1323,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_key_switch(DeviceKeys K, Gate
         if (8 * lane + e < NW) o[8 * lane + e] = acc[e];
 }
 
-// Key switching with eight waves per gate: wave w sums the rows of
-// coefficients 128w .. 128w + 127, the eight partial sums meet in LDS and
-// wave 0 writes the result.  Eight times the waves in flight of the one-wave
-// kernel hides the latency of the row gathers; measured faster at every
-// batch width except 2,305 .. 6,144 gates, where the one-wave kernel, which
-// skips zero digits, wins (6,144 gates: 2.26 vs 3.20 ms; 8,192: 6.05 vs
-// 4.27; 16,384 gates: 8.5 vs 17.3 ms, and 12.4 ms when the rows of a
-// coefficient are staged in LDS once per workgroup of eight gates).  Zero digits read the all-zero
-// row here instead of branching past it: a wave-uniform skip serialises the
-// eight row loads of a coefficient (16,384 gates: 21.3 vs 8.5 ms).
-constexpr int kKsSplitWaves = 8;
-constexpr uint32_t kKsOneWaveMin = 2305, kKsOneWaveMax = 6144;
+// Key switching with W waves per gate: wave w sums the rows of coefficients
+// (N/W) w .. (N/W)(w + 1) - 1, the W partial sums meet in LDS and wave 0
+// writes the result.  SKIP: zero digits (a quarter of them) skip their row
+// by a branch uniform over the wave, at the price of serialising the row
+// loads of a coefficient; otherwise they read the all-zero row.  Per launch
+// width the fastest form was measured (ms per launch; "1" is k_key_switch,
+// which skips):
+//   gates    8 waves   4+skip   2+skip   1
+//   256      0.15      0.35     0.60
+//   1,024    0.56      0.46     0.68     1.05
+//   1,536    0.82      0.62     0.74
+//   2,048    1.07      1.71     0.82     1.13
+//   2,560    1.29      2.31     1.09     1.29
+//   6,144    3.20                        2.26
+//   8,192    4.27                        6.05
+//   16,384   8.52      22.3     20.6     17.3 (without skip)
+// With eight waves a skip costs 8.5 -> 21.3 ms at 16,384 gates, and staging
+// the rows of a coefficient in LDS once per workgroup of eight gates 12.4 ms.
+constexpr uint32_t kKsSplit4Min = 769, kKsSplit2Min = 1793, kKsOneWaveMin = 2817, kKsOneWaveMax = 6144;
 
-__global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceKeys K, GateIO io,
-                                                                        const uint32_t* __restrict__ big,
-                                                                        uint32_t count) {
-    __shared__ uint32_t part[kKsSplitWaves][512];
+template <int W, bool SKIP>
+__global__ __launch_bounds__(64 * W) void k_key_switch_split(DeviceKeys K, GateIO io,
+                                                             const uint32_t* __restrict__ big, uint32_t count) {
+    __shared__ uint32_t part[W][512];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x;
     if (g >= count) return;  // uniform over the block
@@ -1350,7 +1357,7 @@ __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceK
 #pragma unroll
     for (int e = 0; e < 8; ++e) acc[e] = (wave == 0 && 8 * lane + e == NLWE) ? src[N] : 0u;
     const uint4* zero = reinterpret_cast<const uint4*>(K.zero_row);
-    constexpr int kPerWave = N / kKsSplitWaves;  // 128
+    constexpr int kPerWave = N / W;
 #pragma unroll 1
     for (int i0 = wave * kPerWave; i0 < (wave + 1) * kPerWave; i0 += 64) {
         const uint32_t digits = (src[i0 + lane] + (1u << 15)) >> 16;
@@ -1361,6 +1368,7 @@ __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceK
 #pragma unroll
             for (int j = 0; j < (int)kKsT; ++j) {
                 const uint32_t d = (dd >> (14 - 2 * j)) & 3u;
+                if (SKIP && d == 0) continue;
                 const uint4* row = d ? reinterpret_cast<const uint4*>(K.ksk + (rowbase + 3 * j + d - 1) * kKskRowWords)
                                      : zero;
                 const uint4 v0 = row[2 * lane], v1 = row[2 * lane + 1];
@@ -1374,7 +1382,7 @@ __global__ __launch_bounds__(64 * kKsSplitWaves) void k_key_switch_split(DeviceK
     __syncthreads();
     if (wave != 0) return;
 #pragma unroll
-    for (int w = 1; w < kKsSplitWaves; ++w)
+    for (int w = 1; w < W; ++w)
 #pragma unroll
         for (int e = 0; e < 8; ++e) acc[e] += part[w][8 * lane + e];
 #pragma unroll
@@ -1581,9 +1589,13 @@ hipError_t launch_key_switch(const DeviceKeys& K, const GateIO& io, const uint32
     if (count >= kKsOneWaveMin && count <= kKsOneWaveMax) {
         const uint32_t blocks = (count + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL(k_key_switch, dim3(blocks), dim3(kBlockThreads), 0, s, K, io, big, count);
-        return hipGetLastError();
+    } else if (count >= kKsSplit2Min && count < kKsOneWaveMin) {
+        hipLaunchKernelGGL((k_key_switch_split<2, true>), dim3(count), dim3(128), 0, s, K, io, big, count);
+    } else if (count >= kKsSplit4Min && count < kKsSplit2Min) {
+        hipLaunchKernelGGL((k_key_switch_split<4, true>), dim3(count), dim3(256), 0, s, K, io, big, count);
+    } else {
+        hipLaunchKernelGGL((k_key_switch_split<8, false>), dim3(count), dim3(512), 0, s, K, io, big, count);
     }
-    hipLaunchKernelGGL(k_key_switch_split, dim3(count), dim3(64 * kKsSplitWaves), 0, s, K, io, big, count);
     return hipGetLastError();
 }
 

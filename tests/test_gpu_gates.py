@@ -178,12 +178,13 @@ def test_noise_variance_over_16k_bootstraps(env):
     np.testing.assert_array_equal(sk.decrypt_bits(got), want)
 
 
-@pytest.mark.parametrize("n", [16385, 3001, 1537])
+@pytest.mark.parametrize("n", [16385, 3001, 2305, 1537, 513])
 def test_wide_ragged_batch_sampled_bit_exact(env, n):
-    """Wide batches on both key-switching kernels (eight waves per gate at
-    16,385 and 1,537 gates, one wave per gate at 3,001 with a last workgroup
-    of one gate): sampled gates, the first and last among them, bit-exact
-    against the oracle, every gate decrypting to its truth table."""
+    """Wide batches on every key-switching form (eight waves per gate at
+    16,385 and 513 gates, two waves skipping zero digits at 2,305, four at
+    1,537, one wave at 3,001 with a last workgroup of one gate): sampled
+    gates, the first and last among them, bit-exact against the oracle,
+    every gate decrypting to its truth table."""
     sk, ctx, K = env
     ops = workloads.gate_ops(500, n)
     A = workloads.bits(501, n).astype(int)
