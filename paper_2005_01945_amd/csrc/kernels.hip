@@ -271,7 +271,7 @@ constexpr int kTileWords = A == 1 ? 32 * 36 : 32 * 32;
 // Shared-memory footprint of a block of WPB one-wave gates: twiddles plus one
 // accumulator and one pair of tiles per wave (WPB = 4 with the Goldilocks
 // path: 80 KB, so two blocks fit a CU's 160 KB, i.e. two waves per SIMD;
-// WPB = 8 with the two-prime path: 148 KB, one block of two waves per SIMD).
+// WPB = 8 with the two-prime path: 152 KB, one block of two waves per SIMD).
 // Every accumulator polynomial starts at a multiple of 4 KB (rotated_digit_q).
 template <int WPB, int A>
 struct alignas(4096) BlockLds {
