@@ -171,15 +171,18 @@ __device__ __forceinline__ int32_t rotated_digit(const uint32_t* a, uint32_t own
     return __builtin_amdgcn_sbfe((int32_t)(D + doff), shift, 10);
 }
 
-// The same from d4 = 4 d and the LDS byte address abase of the polynomial,
-// a multiple of 4096, so that the word's address is one AND-OR.  The
-// negation is written (v + sgn) ^ sgn, which needs the mask alone (the form
-// (v ^ sgn) - sgn makes the optimiser build -sgn as a second, zero-extended
-// bit): bit-field extract, add, XOR-add, subtract per coefficient.
-__device__ __forceinline__ int32_t rotated_digit_q(uint32_t abase, uint32_t own, int d4, uint32_t doff,
-                                                   int shift) {
-    const lds_u32* p = (const lds_u32*)(uintptr_t)(((uint32_t)d4 & 0xFFCu) | abase);
-    const uint32_t v = *p;
+// The same in two halves, so that the reads can run ahead of the digits:
+// the word's LDS address from d4 = 4 d and the byte address abase of the
+// polynomial, a multiple of 4096, is one AND-OR; the digit from the word v
+// read there.  The negation is written (v + sgn) ^ sgn, which needs the mask
+// alone (the form (v ^ sgn) - sgn makes the optimiser build -sgn as a second,
+// zero-extended bit): bit-field extract, add, XOR-add, subtract per
+// coefficient.
+__device__ __forceinline__ uint32_t rotated_word(uint32_t abase, int d4) {
+    return *(const lds_u32*)(uintptr_t)(((uint32_t)d4 & 0xFFCu) | abase);
+}
+
+__device__ __forceinline__ int32_t rotated_digit_q(uint32_t v, uint32_t own, int d4, uint32_t doff, int shift) {
     const uint32_t sgn = (uint32_t)__builtin_amdgcn_sbfe(d4, 12, 1);
     return __builtin_amdgcn_sbfe((int32_t)(((v + sgn) ^ sgn) + (doff - own)), shift, 10);
 }
@@ -459,12 +462,16 @@ __device__ __forceinline__ void mul8_q(int32_t (&x)[32], const int32_t (&w)[8]) 
 // Table twiddles: x[q] *= tw[q * 32 + t], eight at a time.
 template <int I>
 __device__ __forceinline__ void table_mul_q(int32_t (&x)[32], const int32_t* tw, int t) {
+    int32_t w[2][8];  // the twiddles of chunk c + 1 are read before chunk c is multiplied
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[0][k] = tw[k * 32 + t];
     mq::static_for<0, 4>([&](auto C_) {
         constexpr int c = decltype(C_)::value;
-        int32_t w[8];
+        if constexpr (c < 3) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) w[k] = tw[(8 * c + k) * 32 + t];
-        mul8_q<I, 8 * c>(x, w);
+            for (int k = 0; k < 8; ++k) w[(c + 1) & 1][k] = tw[(8 * c + 8 + k) * 32 + t];
+        }
+        mul8_q<I, 8 * c>(x, w[c & 1]);
     });
 }
 
@@ -592,17 +599,33 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
     prefetch_q<W>(bk0, lane, kw);
     int32_t x[32];
     uint32_t dp[16];
+    // the reads of chunk c + 1 are issued before the digits of chunk c
+    uint32_t rv[2][8], ow[2][8];
+    int dq[2][8];
+    auto issue = [&](auto C_, auto B_) {
+        constexpr int c = decltype(C_)::value, b = decltype(B_)::value;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * c + k;
+            dq[b][k] = d4 + 128 * q;
+            rv[b][k] = rotated_word(abase, dq[b][k]);
+            ow[b][k] = am[32 * q];
+        }
+    };
+    issue(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    mq::static_for<0, 4>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
         sched_fence();
+        if constexpr (c < 3) issue(std::integral_constant<int, c + 1>{}, std::integral_constant<int, (c + 1) & 1>{});
 #pragma unroll
-        for (int q = 8 * c; q < 8 * c + 8; ++q) {
-            x[q] = rotated_digit_q(abase, am[32 * q], d4 + 128 * q, doff, shift);
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * c + k;
+            x[q] = rotated_digit_q(rv[c & 1][k], ow[c & 1][k], dq[c & 1][k], doff, shift);
         }
 #pragma unroll
         for (int j = 4 * c; j < 4 * c + 4; ++j)
             dp[j] = ((uint32_t)x[2 * j] & 0xFFFFu) | ((uint32_t)x[2 * j + 1] << 16);
-    }
+    });
     sched_fence();
     int32_t m0[32], m1[32];
     if constexpr (ACCUM) {
@@ -676,7 +699,8 @@ __device__ __forceinline__ void cmux_finish_q(uint32_t (&acc)[2][1024], uint32_t
 // ACC (half h: polynomial h) += the column given by its residues x0, x1
 // (register r: coefficient t + 32 brv5(r)).
 // Registers 8C..8C+7 of the CRT update below (x0, x1: those registers'
-// residues).  The constants come in scalar registers (crt_consts), so that
+// residues; old: their accumulator words, read ahead by the caller).  The
+// constants come in scalar registers (crt_consts), so that
 // the optimiser keeps the products as multiplies instead of expanding them
 // into shifts and adds of the 2^28 - 2^16 + ... forms of the primes.
 struct CrtConsts {
@@ -689,8 +713,9 @@ __device__ __forceinline__ CrtConsts crt_consts() {
 }
 
 template <int C>
-__device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[8],
-                                            const int32_t (&x1)[8], int lane, const CrtConsts& K) {
+__device__ __forceinline__ void crt_chunk_core(uint32_t (&acc)[2][1024], const int32_t (&x0)[8],
+                                               const int32_t (&x1)[8], int lane, const CrtConsts& K,
+                                               const uint32_t (&old)[8]) {
     const int h = lane >> 5, t = lane & 31;
     uint32_t* mine = acc[h] + t;
     int32_t d[8];
@@ -709,15 +734,23 @@ __device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int3
 #pragma unroll
     for (int k = 0; k < 8; ++k) m[k] = (int32_t)((uint32_t)p[k] * mq::Mod<1>::qinv);
     sched_fence();
-    uint32_t old[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * C + k)];
 #pragma unroll
     for (int k = 0; k < 8; ++k) d[k] = (int32_t)((p[k] + (int64_t)m[k] * K.nq1) >> 32);
     sched_fence();
 #pragma unroll
     for (int k = 0; k < 8; ++k) mine[32 * brv5(8 * C + k)] = old[k] + (uint32_t)x0[k] + (uint32_t)K.q0 * (uint32_t)d[k];
     sched_fence();
+}
+
+// The same, reading the chunk's accumulator words itself.
+template <int C>
+__device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[8],
+                                            const int32_t (&x1)[8], int lane, const CrtConsts& K) {
+    const uint32_t* mine = acc[lane >> 5] + (lane & 31);
+    uint32_t old[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) old[k] = mine[32 * brv5(8 * C + k)];
+    crt_chunk_core<C>(acc, x0, x1, lane, K, old);
 }
 
 // Residues (|v0| < q0, |v1| < q1) of an integer V with |V| <= 2^52 ->
@@ -731,15 +764,23 @@ __device__ __forceinline__ void crt_chunk_q(uint32_t (&acc)[2][1024], const int3
 __device__ __forceinline__ void crt_update_q(uint32_t (&acc)[2][1024], const int32_t (&x0)[32],
                                              const int32_t (&x1)[32], int lane) {
     const CrtConsts K = crt_consts();
+    const uint32_t* mine = acc[lane >> 5] + (lane & 31);
+    uint32_t old[2][8];  // the words of chunk c + 1 are read before chunk c is updated
+#pragma unroll
+    for (int k = 0; k < 8; ++k) old[0][k] = mine[32 * brv5(k)];
     mq::static_for<0, 4>([&](auto C_) {
         constexpr int c = decltype(C_)::value;
+        if constexpr (c < 3) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) old[(c + 1) & 1][k] = mine[32 * brv5(8 * c + 8 + k)];
+        }
         int32_t a0[8], a1[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             a0[k] = x0[8 * c + k];
             a1[k] = x1[8 * c + k];
         }
-        crt_chunk_q<c>(acc, a0, a1, lane, K);
+        crt_chunk_core<c>(acc, a0, a1, lane, K, old[c & 1]);
     });
 }
 
