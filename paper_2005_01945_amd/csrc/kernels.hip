@@ -156,28 +156,21 @@ __device__ __forceinline__ const lds_u32* lds_column(const uint32_t* a, int t) {
 
 // Gadget digit of coefficient m of D = X^ai ACC - ACC for this half (digit
 // h of two: bits 22..31 for h = 0, 12..21 for h = 1), in [-512, 511], from
-// d = m - ai.  d needs no reduction: its bits 0..9 are d mod 1024 (the word
-// read) and its bit 10 tells whether d mod 2048 >= 1024 (X^N = -1: the word
-// is negated), for negative d too.  doff is the rounding offset of both
-// digits plus 2^(shift + 9), which makes the signed 10-bit field equal to
-// the unsigned field minus 512.
+// d4 = 4 (m - ai).  d4 needs no reduction: its bits 2..11 are (m - ai) mod
+// 1024 times 4, the byte offset of the word read, and its bit 12 tells
+// whether (m - ai) mod 2048 >= 1024 (X^N = -1: the word is negated), for
+// negative m - ai too.  doff is the rounding offset of both digits plus
+// 2^(shift + 9), which makes the signed 10-bit field equal to the unsigned
+// field minus 512.
 __device__ __forceinline__ uint32_t digit_offset(int h) { return kDecompOffset + (1u << (31 - 10 * h)); }
 
-__device__ __forceinline__ int32_t rotated_digit(const uint32_t* a, uint32_t own, int d, uint32_t doff,
-                                                 int shift) {
-    const uint32_t v = a[d & 1023];
-    const uint32_t sgn = (uint32_t)__builtin_amdgcn_sbfe(d, 10, 1);
-    const uint32_t D = ((v ^ sgn) - sgn) - own;
-    return __builtin_amdgcn_sbfe((int32_t)(D + doff), shift, 10);
-}
-
-// The same in two halves, so that the reads can run ahead of the digits:
-// the word's LDS address from d4 = 4 d and the byte address abase of the
-// polynomial, a multiple of 4096, is one AND-OR; the digit from the word v
-// read there.  The negation is written (v + sgn) ^ sgn, which needs the mask
-// alone (the form (v ^ sgn) - sgn makes the optimiser build -sgn as a second,
-// zero-extended bit): bit-field extract, add, XOR-add, subtract per
-// coefficient.
+// The digit in two halves, so that the reads can run ahead of the digits:
+// the word's LDS address, with abase the byte address of the polynomial (a
+// multiple of 4096), is one AND-OR; the digit comes from the word v read
+// there and the unrotated word own.  The negation is written (v + sgn) ^
+// sgn, which needs the mask alone (the form (v ^ sgn) - sgn makes the
+// optimiser build -sgn as a second, zero-extended bit): bit-field extract,
+// add, XOR-add, subtract per coefficient.
 __device__ __forceinline__ uint32_t rotated_word(uint32_t abase, int d4) {
     return *(const lds_u32*)(uintptr_t)(((uint32_t)d4 & 0xFFCu) | abase);
 }
@@ -303,13 +296,14 @@ static_assert(offsetof(PairLds<1>, acc) % 4096 == 0, "accumulators must be 4 KB 
 // only, 74 KB): wave w = 2 hp + prime runs pass hp in that prime; the pass-1
 // waves hand their column sums to the pass-0 waves through `part`, which
 // finish their prime; wave 1 hands its residues to wave 0, which recombines.
-struct QuadLds {
+struct alignas(4096) QuadLds {
     uint64_t twf[32 * 32];
     uint64_t twi[32 * 32];
     uint32_t acc[2][1024];
     uint32_t tile[4][2][32 * 36];  // [wave][half]
     int32_t part[2][32][64];       // [prime][register][lane]
 };
+static_assert(offsetof(QuadLds, acc) % 4096 == 0, "accumulators must be 4 KB aligned");
 
 // Pass HP of a CMux step: D = X^ai ACC_HP - ACC_HP (a = ACC_HP), this half's
 // gadget digit of it (half h extracts digit h), its forward NTT, then the
@@ -660,20 +654,37 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
     const int shift = 22 - 10 * h;
     const uint32_t doff = digit_offset(h);
     const lds_u32* am = lds_column(a, t);
-    int d0 = t - ai;  // opaque: the pass forms its own indices instead of keeping them
-    asm volatile("" : "+v"(d0));
+    const uint32_t abase = (uint32_t)(uintptr_t)(const lds_u32*)a;
+    int d4 = 4 * (t - ai);  // opaque: the pass forms its own addresses instead of keeping them
+    asm volatile("" : "+v"(d4));
     const uint32_t* bk = reinterpret_cast<const uint32_t*>(bk_i) + HP * 8192 + I * 4096;
     KeyWindow<W> kw;
     prefetch_q<W>(bk, lane, kw);
     int32_t x[32];
+    // the reads of chunk c + 1 are issued before the digits of chunk c
+    uint32_t rv[2][8], ow[2][8];
+    int dq[2][8];
+    auto issue = [&](auto C_, auto B_) {
+        constexpr int c = decltype(C_)::value, b = decltype(B_)::value;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        sched_fence();
-#pragma unroll
-        for (int q = 8 * c; q < 8 * c + 8; ++q) {
-            x[q] = rotated_digit(a, am[32 * q], d0 + 32 * q, doff, shift);
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * c + k;
+            dq[b][k] = d4 + 128 * q;
+            rv[b][k] = rotated_word(abase, dq[b][k]);
+            ow[b][k] = am[32 * q];
         }
-    }
+    };
+    issue(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    mq::static_for<0, 4>([&](auto C_) {
+        constexpr int c = decltype(C_)::value;
+        sched_fence();
+        if constexpr (c < 3) issue(std::integral_constant<int, c + 1>{}, std::integral_constant<int, (c + 1) & 1>{});
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * c + k;
+            x[q] = rotated_digit_q(rv[c & 1][k], ow[c & 1][k], dq[c & 1][k], doff, shift);
+        }
+    });
     sched_fence();
     ntt1024_fwd_q<I>(x, tile, twf + I * 1024, t);
     mac_q<I, false, W>(x, bk, kw, lane, mac);
