@@ -160,9 +160,11 @@ int fhe_phase(const fhe_secret_key* sk, const uint32_t* ct, size_t count, int32_
 /* ---------------------------------------------------------------------- */
 
 /* Uploads the cloud key to HIP device `device`, converts the bootstrapping
- * key to the NTT domain over p = 2^64 - 2^32 + 1 (32.8 MB) and lays out the
+ * key to the NTT domains of both arithmetics (modulo two 28-bit primes, the
+ * default, and over p = 2^64 - 2^32 + 1; 32.8 MB each) and lays out the
  * key-switching key for row gathers (50.3 MB).  The cloud key may be freed
- * afterwards.  Errors: FHE_EDEVICE if the device is missing or not gfx950. */
+ * afterwards.  Errors: FHE_EDEVICE if the device is missing or not gfx950;
+ * FHE_ENOMEM if device memory runs out. */
 int fhe_ctx_create(const fhe_cloud_key* ck, int device, fhe_ctx** out);
 void fhe_ctx_destroy(fhe_ctx* ctx);
 
