@@ -1540,7 +1540,8 @@ __global__ __launch_bounds__(64) void k_debug_cmux(DeviceKeys K, const uint64_t*
 }
 
 // Issue-rate probe of one VALU instruction class (the roofline's peak per
-// class): every lane runs 16 independent chains of the instruction, 64 per
+// class): every lane runs 16 independent chains of the instruction (eight
+// for the swap, which writes two registers), 64 instructions per
 // iteration.  Only arithmetic instructions, no memory access but the final
 // store of each lane's sum into out[global thread index].
 template <int OP>
@@ -1564,8 +1565,8 @@ __global__ __launch_bounds__(256) void k_valu_probe(uint32_t* __restrict__ out, 
                     asm volatile("v_mad_i64_i32 %0, vcc, %1, %2, %0" : "+v"(w[k]) : "v"(b), "v"(c) : "vcc");
                 if constexpr (OP == 3) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 if constexpr (OP == 4) asm volatile("v_bfe_i32 %0, %0, %1, 10" : "+v"(a[k]) : "v"(c));
-                if constexpr (OP == 5)
-                    asm volatile("v_permlane32_swap_b32 %0, %1" : "+v"(a[k]), "+v"(a[(k + 1) & 15]));
+                if constexpr (OP == 5)  // eight disjoint register pairs, each swapped twice per pass
+                    asm volatile("v_permlane32_swap_b32 %0, %1" : "+v"(a[k & 7]), "+v"(a[8 + (k & 7)]));
             }
         }
     }
