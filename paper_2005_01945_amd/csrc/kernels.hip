@@ -422,6 +422,10 @@ __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, 
     typedef __attribute__((address_space(3))) v4u lds_u4;
     lds_u4* row = (lds_u4*)(tile + 36 * t);
     asm volatile("" : "+v"(row));
+    // LDS phases take the highest issue priority (the transforms have 1): a
+    // wave about to wait on LDS gets its requests out first, then the SIMD's
+    // other wave computes under the latency
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int k = 0; k < 32; ++k) col[wr(k) * 36] = (uint32_t)x[k];
     wave_lds_sync();
@@ -433,6 +437,7 @@ __device__ __forceinline__ void transpose32_w(int32_t (&x)[32], uint32_t* tile, 
         x[4 * g + 2] = (int32_t)v.z;
         x[4 * g + 3] = (int32_t)v.w;
     }
+    __builtin_amdgcn_s_setprio(0);
     wave_lds_sync();
 }
 
@@ -598,6 +603,7 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
     int dq[2][8];
     auto issue = [&](auto C_, auto B_) {
         constexpr int c = decltype(C_)::value, b = decltype(B_)::value;
+        __builtin_amdgcn_s_setprio(2);  // as in transpose32_w
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int q = 8 * c + k;
@@ -605,6 +611,7 @@ __device__ __forceinline__ void cmux_pass_q(const uint32_t* a, uint32_t* tile, i
             rv[b][k] = rotated_word(abase, dq[b][k]);
             ow[b][k] = am[32 * q];
         }
+        __builtin_amdgcn_s_setprio(0);
     };
     issue(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
     mq::static_for<0, 4>([&](auto C_) {
@@ -666,6 +673,7 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
     int dq[2][8];
     auto issue = [&](auto C_, auto B_) {
         constexpr int c = decltype(C_)::value, b = decltype(B_)::value;
+        __builtin_amdgcn_s_setprio(2);  // as in transpose32_w
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int q = 8 * c + k;
@@ -673,6 +681,7 @@ __device__ __forceinline__ void cmux_pass_q1(const uint32_t* a, uint32_t* tile, 
             rv[b][k] = rotated_word(abase, dq[b][k]);
             ow[b][k] = am[32 * q];
         }
+        __builtin_amdgcn_s_setprio(0);
     };
     issue(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
     mq::static_for<0, 4>([&](auto C_) {
